@@ -1,0 +1,109 @@
+/*
+ * Sequential CPU oracle for the prefix-sum hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or build flag
+ * with the HIP kernels.
+ *
+ * What it computes (Introduction, definition of the scan):
+ *   inclusive  out[i] = a[0] (+) a[1] (+) ... (+) a[i]
+ *   exclusive  out[0] = identity, out[i] = a[0] (+) ... (+) a[i-1]
+ * with (+) = addition, evaluated exactly as the basic algorithm the
+ * Introduction describes: one sequential pass of additions over the input,
+ * writing the running total.  Section 2 (thread-level parallelism) allows the
+ * output to overwrite the input (in place); every routine here reads a[i]
+ * before it writes out[i], so out == a is legal.
+ *
+ * Integer element types add in uint32_t, i.e. modulo 2^32 (the paper is silent
+ * on overflow; wrap-around is the reading taken).  32-bit signed data is the
+ * same bit pattern.  Float32 inputs are accumulated in float64 (the paper
+ * notes that parallel float results may differ from the sequential ones; the
+ * oracle therefore computes the sequential sum in a wider type and also
+ * returns the running sum of absolute values, which sets the tolerance).
+ *
+ * Extensions that the paper does not define, read as follows:
+ *   reverse   out[i] = a[i] (+) a[i+1] (+) ... (+) a[n-1]   (suffix scan; the
+ *             exclusive form drops a[i]) -- the sequential pass runs from the
+ *             last element down to the first;
+ *   segmented offsets[0..S] (CSR form, offsets[0]=0, non-decreasing,
+ *             offsets[S]=n) split the array into S independent segments;
+ *             the running total restarts at the identity at each segment
+ *             boundary, so each segment's result is the plain scan of that
+ *             segment.  Empty segments are allowed.
+ *
+ * Build: gcc -O2 -std=c99 -shared -fPIC (no -ffast-math: the float64
+ * additions must happen in program order).
+ */
+#include <stdint.h>
+#include <math.h>
+
+/* ---- flat scans -------------------------------------------------------- */
+
+void oracle_scan_u32(const uint32_t *a, uint32_t *out, int64_t n,
+                     int exclusive, int reverse)
+{
+    uint32_t acc = 0u;
+    if (!reverse) {
+        for (int64_t i = 0; i < n; ++i) {
+            uint32_t x = a[i];
+            if (exclusive) { out[i] = acc; acc += x; }
+            else           { acc += x; out[i] = acc; }
+        }
+    } else {
+        for (int64_t i = n - 1; i >= 0; --i) {
+            uint32_t x = a[i];
+            if (exclusive) { out[i] = acc; acc += x; }
+            else           { acc += x; out[i] = acc; }
+        }
+    }
+}
+
+/* out[i]: the sequential float64 prefix sum of the float32 inputs;
+ * abs_out[i]: the same running sum over |a[j]| (may be NULL). */
+void oracle_scan_f32_f64(const float *a, double *out, double *abs_out,
+                         int64_t n, int exclusive, int reverse)
+{
+    double acc = 0.0, aacc = 0.0;
+    int64_t i = reverse ? n - 1 : 0;
+    int64_t step = reverse ? -1 : 1;
+    for (int64_t k = 0; k < n; ++k, i += step) {
+        double x = (double)a[i];
+        if (exclusive) {
+            out[i] = acc;
+            if (abs_out) abs_out[i] = aacc;
+            acc += x;
+            aacc += fabs(x);
+        } else {
+            acc += x;
+            aacc += fabs(x);
+            out[i] = acc;
+            if (abs_out) abs_out[i] = aacc;
+        }
+    }
+}
+
+/* ---- segmented scans --------------------------------------------------- */
+
+void oracle_segmented_u32(const uint32_t *a, uint32_t *out,
+                          const int64_t *offsets, int64_t num_segments,
+                          int exclusive, int reverse)
+{
+    for (int64_t s = 0; s < num_segments; ++s) {
+        int64_t lo = offsets[s], hi = offsets[s + 1];
+        if (hi > lo)
+            oracle_scan_u32(a + lo, out + lo, hi - lo, exclusive, reverse);
+    }
+}
+
+void oracle_segmented_f32_f64(const float *a, double *out, double *abs_out,
+                              const int64_t *offsets, int64_t num_segments,
+                              int exclusive, int reverse)
+{
+    for (int64_t s = 0; s < num_segments; ++s) {
+        int64_t lo = offsets[s], hi = offsets[s + 1];
+        if (hi > lo)
+            oracle_scan_f32_f64(a + lo, out + lo, abs_out ? abs_out + lo : 0,
+                                hi - lo, exclusive, reverse);
+    }
+}

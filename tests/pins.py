@@ -1,0 +1,266 @@
+"""Pins for the sequential oracle: checks that do not use the oracle itself.
+
+Each ``pin_*`` function takes an implementation with the oracle's call
+signature and returns a list of failure strings (empty = pinned).  The real
+oracle must pass them all; ``test_oracle.py`` also plants plausible mistakes
+in copies of the oracle and checks that some pin catches each one.
+
+Sources of truth (none of them is the oracle):
+  * hand-computed fixtures under tests/golden/ (definition in the Introduction),
+  * closed forms (constant and arithmetic-progression inputs),
+  * brute force from the definition in pure Python integers / fractions,
+  * numpy's own cumulative sums (uint32 wraps; float64 add.accumulate runs
+    left to right),
+  * invariants (last inclusive value = total, inclusive - exclusive = input,
+    linearity modulo 2^32, in place = out of place).
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+
+import numpy as np
+
+import golden_io
+
+M32 = 1 << 32
+
+
+def _brute_int(a, exclusive, reverse):
+    """O(n^2) scan straight from the definition, in Python integers mod 2^32."""
+    a = [int(x) % M32 for x in a]
+    n = len(a)
+    out = []
+    for i in range(n):
+        if not reverse:
+            idx = range(0, i) if exclusive else range(0, i + 1)
+        else:
+            idx = range(i + 1, n) if exclusive else range(i, n)
+        out.append(sum(a[j] for j in idx) % M32)
+    return out
+
+
+def _cmp(name, got, want, fails):
+    got = [int(x) for x in np.asarray(got).view(np.uint32)] if np.asarray(got).dtype.kind in "iu" else list(got)
+    want = [int(x) % M32 for x in want]
+    if got != want:
+        bad = next(i for i, (g, w) in enumerate(zip(got, want)) if g != w) if len(got) == len(want) else -1
+        fails.append("%s: mismatch (first at %d)" % (name, bad))
+
+
+# ---------------------------------------------------------------- integers
+
+def pin_int_flat(scan_int) -> list:
+    """scan_int(a, exclusive, reverse) -> array, wrapping modulo 2^32."""
+    fails = []
+    g = golden_io.load("definition_small.txt")
+    a = np.array(g["input"], dtype=np.uint32)
+    _cmp("golden inclusive", scan_int(a, False, False), g["inclusive"], fails)
+    _cmp("golden exclusive", scan_int(a, True, False), g["exclusive"], fails)
+    _cmp("golden reverse inclusive", scan_int(a, False, True), g["reverse_inclusive"], fails)
+    _cmp("golden reverse exclusive", scan_int(a, True, True), g["reverse_exclusive"], fails)
+    w = golden_io.load("wrap_u32.txt")
+    a = np.array(w["input"], dtype=np.uint32)
+    _cmp("golden wrap inclusive", scan_int(a, False, False), w["inclusive"], fails)
+    _cmp("golden wrap exclusive", scan_int(a, True, False), w["exclusive"], fails)
+
+    # closed form: all ones -> i+1 (inclusive), i (exclusive); reverse n-i / n-1-i
+    n = 5000
+    ones = np.ones(n, dtype=np.uint32)
+    i = np.arange(n, dtype=np.int64)
+    _cmp("ones inclusive", scan_int(ones, False, False), i + 1, fails)
+    _cmp("ones exclusive", scan_int(ones, True, False), i, fails)
+    _cmp("ones reverse inclusive", scan_int(ones, False, True), n - i, fails)
+    _cmp("ones reverse exclusive", scan_int(ones, True, True), n - 1 - i, fails)
+
+    # closed form: a_i = c + d*i  ->  (i+1)c + d*i(i+1)/2  (mod 2^32), chosen to wrap
+    c, d = 3_000_000_007 % M32, 2_654_435_761
+    n = 20000
+    a = np.array([(c + d * k) % M32 for k in range(n)], dtype=np.uint32)
+    want = [((k + 1) * c + d * k * (k + 1) // 2) % M32 for k in range(n)]
+    _cmp("arithmetic progression inclusive", scan_int(a, False, False), want, fails)
+    want_ex = [(k * c + d * (k - 1) * k // 2) % M32 for k in range(n)]
+    _cmp("arithmetic progression exclusive", scan_int(a, True, False), want_ex, fails)
+
+    # brute force from the definition on small random inputs, every mode
+    rng = np.random.default_rng(7)
+    for n in (0, 1, 2, 3, 17, 64, 65, 257):
+        a = rng.integers(0, M32, size=n, dtype=np.uint32)
+        for ex in (False, True):
+            for rev in (False, True):
+                _cmp("brute n=%d ex=%d rev=%d" % (n, ex, rev),
+                     scan_int(a, ex, rev), _brute_int(a, ex, rev), fails)
+
+    # numpy's wrapping uint32 cumsum (forward) and its flip (reverse)
+    a = rng.integers(0, M32, size=100_003, dtype=np.uint32)
+    _cmp("numpy cumsum uint32", scan_int(a, False, False), np.cumsum(a, dtype=np.uint32), fails)
+    _cmp("numpy flipped cumsum", scan_int(a, False, True),
+         np.cumsum(a[::-1], dtype=np.uint32)[::-1], fails)
+
+    # invariants: last = total, inclusive - exclusive = input, linearity, in place
+    inc = np.asarray(scan_int(a, False, False)).view(np.uint32)
+    exc = np.asarray(scan_int(a, True, False)).view(np.uint32)
+    total = int(a.astype(np.uint64).sum()) % M32
+    if int(inc[-1]) != total:
+        fails.append("last inclusive != total")
+    if not np.array_equal(inc - exc, a):
+        fails.append("inclusive - exclusive != input")
+    b = rng.integers(0, M32, size=a.size, dtype=np.uint32)
+    lin = np.asarray(scan_int(a + b, False, False)).view(np.uint32)
+    if not np.array_equal(lin, inc + np.asarray(scan_int(b, False, False)).view(np.uint32)):
+        fails.append("scan(a+b) != scan(a)+scan(b) mod 2^32")
+    # signed view: int32 input gives the same bits as uint32
+    s = np.asarray(scan_int(a.view(np.int32), False, False))
+    if s.dtype != np.int32 or not np.array_equal(s.view(np.uint32), inc):
+        fails.append("int32 view differs from uint32")
+    return fails
+
+
+def pin_int_inplace(scan_int_out) -> list:
+    """scan_int_out(a, exclusive, reverse, out) with out == a."""
+    fails = []
+    rng = np.random.default_rng(11)
+    for ex in (False, True):
+        for rev in (False, True):
+            a = rng.integers(0, M32, size=4099, dtype=np.uint32)
+            want = _brute_int(a[:300], ex, rev) if not rev else None
+            ref = np.cumsum(a, dtype=np.uint32) if not rev else np.cumsum(a[::-1], dtype=np.uint32)[::-1]
+            if ex:
+                ref = (ref - a).astype(np.uint32)
+            buf = a.copy()
+            scan_int_out(buf, ex, rev, buf)
+            if not np.array_equal(buf, ref):
+                fails.append("in place ex=%d rev=%d" % (ex, rev))
+            if want is not None and [int(x) for x in buf[:300]] != want:
+                fails.append("in place brute ex=%d" % ex)
+    return fails
+
+
+def pin_int_segmented(seg_int, scan_int_brute=_brute_int) -> list:
+    """seg_int(a, offsets, exclusive, reverse) -> array."""
+    fails = []
+    g = golden_io.load("segmented_small.txt")
+    a = np.array(g["input"], dtype=np.uint32)
+    off = np.array(g["offsets"], dtype=np.int64)
+    _cmp("golden seg inclusive", seg_int(a, off, False, False), g["inclusive"], fails)
+    _cmp("golden seg exclusive", seg_int(a, off, True, False), g["exclusive"], fails)
+    _cmp("golden seg reverse inclusive", seg_int(a, off, False, True), g["reverse_inclusive"], fails)
+
+    rng = np.random.default_rng(13)
+    for n, S in ((1, 1), (50, 1), (50, 7), (400, 40), (300, 300), (257, 90)):
+        a = rng.integers(0, M32, size=n, dtype=np.uint32)
+        if S == 1:
+            off = np.array([0, n], dtype=np.int64)
+        else:
+            cuts = np.sort(rng.integers(0, n + 1, size=S - 1))
+            off = np.concatenate([[0], cuts, [n]]).astype(np.int64)
+        for ex in (False, True):
+            for rev in (False, True):
+                want = []
+                for s in range(S):
+                    want += scan_int_brute(a[off[s]:off[s + 1]], ex, rev)
+                _cmp("seg brute n=%d S=%d ex=%d rev=%d" % (n, S, ex, rev),
+                     seg_int(a, off, ex, rev), want, fails)
+    # all length-1 segments: inclusive = input, exclusive = 0
+    n = 1000
+    a = rng.integers(0, M32, size=n, dtype=np.uint32)
+    off = np.arange(n + 1, dtype=np.int64)
+    _cmp("length-1 inclusive", seg_int(a, off, False, False), a, fails)
+    _cmp("length-1 exclusive", seg_int(a, off, True, False), np.zeros(n, dtype=np.int64), fails)
+    # a single segment is the flat scan (numpy wrapping cumsum)
+    a = rng.integers(0, M32, size=10_000, dtype=np.uint32)
+    _cmp("single segment = flat", seg_int(a, np.array([0, a.size]), False, False),
+         np.cumsum(a, dtype=np.uint32), fails)
+    return fails
+
+
+# ---------------------------------------------------------------- floats
+
+def _fcmp(name, got, want, fails, exact=True, tol=None):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    if got.shape != want.shape:
+        fails.append("%s: shape %s vs %s" % (name, got.shape, want.shape))
+        return
+    if exact:
+        if not np.array_equal(got, want):
+            fails.append("%s: not bit-equal (first at %d)" % (name, int(np.argmax(got != want))))
+    else:
+        err = np.abs(got - want)
+        if np.any(err > tol):
+            fails.append("%s: error %.3g above bound at %d" % (name, float(err.max()), int(np.argmax(err > tol))))
+
+
+def pin_f32(scan_f32) -> list:
+    """scan_f32(a, exclusive, reverse) -> (sums float64, abs_sums float64)."""
+    fails = []
+    g = golden_io.load("float_small.txt", conv=float)
+    a = np.array(g["input"], dtype=np.float32)
+    s, ab = scan_f32(a, False, False)
+    _fcmp("golden f inclusive", s, g["inclusive"], fails)
+    _fcmp("golden f abs", ab, g["abs_inclusive"], fails)
+    s, _ = scan_f32(a, True, False)
+    _fcmp("golden f exclusive", s, g["exclusive"], fails)
+
+    rng = np.random.default_rng(17)
+    # integer-valued inputs: every partial sum exact -> integer cumsum
+    a = rng.integers(-1000, 1001, size=50_000).astype(np.float32)
+    ai = a.astype(np.int64)
+    for ex in (False, True):
+        for rev in (False, True):
+            v = ai[::-1] if rev else ai
+            ref = np.cumsum(v)
+            if ex:
+                ref = ref - v
+            if rev:
+                ref = ref[::-1]
+            s, ab = scan_f32(a, ex, rev)
+            _fcmp("int-valued ex=%d rev=%d" % (ex, rev), s, ref, fails)
+            vabs = np.abs(v)
+            rab = np.cumsum(vabs) - (vabs if ex else 0)
+            _fcmp("abs int-valued ex=%d rev=%d" % (ex, rev), ab, rab[::-1] if rev else rab, fails)
+
+    # numpy's float64 add.accumulate runs left to right: bit-equal
+    a = rng.standard_normal(100_001).astype(np.float32)
+    s, _ = scan_f32(a, False, False)
+    _fcmp("numpy add.accumulate f64", s, np.add.accumulate(a.astype(np.float64)), fails)
+    s, _ = scan_f32(a, False, True)
+    _fcmp("numpy flipped accumulate f64", s, np.add.accumulate(a[::-1].astype(np.float64))[::-1], fails)
+
+    # exact rational prefix sums on a small random input: the sequential float64
+    # sum is within (i) * 2^-53 * sum|a| of the exact value (standard bound)
+    a = rng.standard_normal(600).astype(np.float32)
+    s, ab = scan_f32(a, False, False)
+    exact = []
+    acc = Fraction(0)
+    for x in a:
+        acc += Fraction(float(x))
+        exact.append(acc)
+    for k in range(len(a)):
+        bound = (k + 1) * 2.0**-53 * float(ab[k]) * 1.0000001
+        if abs(Fraction(float(s[k])) - exact[k]) > Fraction(bound):
+            fails.append("rational bound at %d" % k)
+            break
+    if abs(float(s[-1]) - math.fsum(float(x) for x in a)) > len(a) * 2.0**-53 * float(ab[-1]):
+        fails.append("fsum total")
+    return fails
+
+
+def pin_f32_segmented(seg_f32) -> list:
+    fails = []
+    rng = np.random.default_rng(19)
+    n = 3000
+    a = rng.integers(-50, 51, size=n).astype(np.float32)
+    cuts = np.sort(rng.integers(0, n + 1, size=39))
+    off = np.concatenate([[0], cuts, [n]]).astype(np.int64)
+    for ex in (False, True):
+        for rev in (False, True):
+            want = []
+            for s in range(len(off) - 1):
+                seg = a[off[s]:off[s + 1]].astype(np.int64)
+                v = seg[::-1] if rev else seg
+                c = np.cumsum(v) - (v if ex else 0)
+                want.append(c[::-1] if rev else c)
+            s, _ = seg_f32(a, off, ex, rev)
+            _fcmp("seg f ex=%d rev=%d" % (ex, rev), s, np.concatenate(want), fails)
+    return fails

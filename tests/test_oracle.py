@@ -1,0 +1,147 @@
+"""The oracle against its pins (no GPU), plus planted mistakes that the pins
+must catch.  Every mutant is a copy of the oracle with one plausible error."""
+import numpy as np
+import pytest
+
+import oracle
+import pins
+
+
+def _int(a, ex, rev):
+    return oracle.scan_int(a, exclusive=ex, reverse=rev)
+
+
+def _int_out(a, ex, rev, out):
+    return oracle.scan_int(a, exclusive=ex, reverse=rev, out=out)
+
+
+def _seg(a, off, ex, rev):
+    return oracle.segmented_int(a, off, exclusive=ex, reverse=rev)
+
+
+def _f(a, ex, rev):
+    return oracle.scan_f32(a, exclusive=ex, reverse=rev)
+
+
+def _segf(a, off, ex, rev):
+    return oracle.segmented_f32(a, off, exclusive=ex, reverse=rev)
+
+
+def test_oracle_int_flat_pinned():
+    assert pins.pin_int_flat(_int) == []
+
+
+def test_oracle_int_inplace_pinned():
+    assert pins.pin_int_inplace(_int_out) == []
+
+
+def test_oracle_int_segmented_pinned():
+    assert pins.pin_int_segmented(_seg) == []
+
+
+def test_oracle_f32_pinned():
+    assert pins.pin_f32(_f) == []
+
+
+def test_oracle_f32_segmented_pinned():
+    assert pins.pin_f32_segmented(_segf) == []
+
+
+def test_tolerance_scale():
+    s, ab = oracle.scan_f32(np.array([1.0, -3.0], dtype=np.float32))
+    assert np.array_equal(oracle.f32_tolerance(ab), np.array([1.0, 4.0]) * 2.0**-20)
+
+
+def test_offsets_validation():
+    a = np.zeros(4, dtype=np.int32)
+    with pytest.raises(ValueError):
+        oracle.segmented_int(a, np.array([1, 4]))
+    with pytest.raises(ValueError):
+        oracle.segmented_int(a, np.array([0, 3]))
+    with pytest.raises(ValueError):
+        oracle.segmented_int(a, np.array([0, 3, 2, 4]))
+
+
+# ------------------------------------------------------------ planted mistakes
+
+def _m_exclusive_is_inclusive(a, ex, rev):
+    return oracle.scan_int(a, exclusive=False, reverse=rev)
+
+
+def _m_dropped_first_term(a, ex, rev):
+    out = np.asarray(oracle.scan_int(a, exclusive=ex, reverse=rev)).view(np.uint32).copy()
+    if out.size and not rev:
+        first = np.asarray(a).view(np.uint32)[0]
+        out[1:] -= first  # a[0] missing from every later prefix
+    return out
+
+
+def _m_reverse_ignored(a, ex, rev):
+    return oracle.scan_int(a, exclusive=ex, reverse=False)
+
+
+def _m_saturating(a, ex, rev):
+    v = np.asarray(a).view(np.uint32).astype(np.int64)
+    if rev:
+        v = v[::-1]
+    c = np.cumsum(v) - (v if ex else 0)
+    c = np.minimum(c, 2**32 - 1)  # no wrap-around
+    return (c[::-1] if rev else c).astype(np.uint32)
+
+
+def _m_off_by_one_shift(a, ex, rev):
+    out = np.asarray(oracle.scan_int(a, exclusive=ex, reverse=rev)).view(np.uint32)
+    return np.roll(out, 1)
+
+
+def _m_seg_no_restart_after_empty(a, off, ex, rev):
+    # drops empty segments' boundaries AND merges the segment after an empty one
+    off = np.asarray(off)
+    keep = [0]
+    for s in range(1, len(off)):
+        if off[s] != off[s - 1] or s == len(off) - 1:
+            keep.append(s)
+        else:
+            keep.pop() if len(keep) > 1 else None
+    return oracle.segmented_int(a, off[np.array(sorted(set(keep)))], exclusive=ex, reverse=rev)
+
+
+def _m_seg_restart_late(a, off, ex, rev):
+    off = np.asarray(off).copy()
+    n = int(off[-1])
+    off[1:-1] = np.minimum(off[1:-1] + 1, n)
+    off = np.maximum.accumulate(off)
+    return oracle.segmented_int(a, off, exclusive=ex, reverse=rev)
+
+
+def _m_f32_accumulator(a, ex, rev):
+    v = np.asarray(a, dtype=np.float32)
+    if rev:
+        v = v[::-1]
+    c = np.cumsum(v, dtype=np.float32).astype(np.float64)
+    if ex:
+        c = c - v
+    ab = np.cumsum(np.abs(v).astype(np.float64)) - (np.abs(v) if ex else 0)
+    return (c[::-1], ab[::-1]) if rev else (c, ab)
+
+
+def _m_abs_signed(a, ex, rev):
+    s, _ = oracle.scan_f32(a, exclusive=ex, reverse=rev)
+    return s, s.copy()
+
+
+@pytest.mark.parametrize("mutant", [
+    _m_exclusive_is_inclusive, _m_dropped_first_term, _m_reverse_ignored,
+    _m_saturating, _m_off_by_one_shift])
+def test_pins_catch_int_mutant(mutant):
+    assert pins.pin_int_flat(mutant) != []
+
+
+@pytest.mark.parametrize("mutant", [_m_seg_no_restart_after_empty, _m_seg_restart_late])
+def test_pins_catch_segmented_mutant(mutant):
+    assert pins.pin_int_segmented(mutant) != []
+
+
+@pytest.mark.parametrize("mutant", [_m_f32_accumulator, _m_abs_signed])
+def test_pins_catch_f32_mutant(mutant):
+    assert pins.pin_f32(mutant) != []
