@@ -1,0 +1,180 @@
+/*
+ * mi355scan -- single-pass prefix sums (scans) on AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the scan of the paper's Introduction: for an input
+ * a[0..n-1] and the operator +, the inclusive scan writes
+ *     out[i] = a[0] + a[1] + ... + a[i]
+ * and the exclusive scan writes the identity (0) first and drops the last
+ * inclusive value:  out[0] = 0, out[i] = a[0] + ... + a[i-1].
+ * Section 2 (thread-level parallelism) allows the result to replace the input:
+ * in == out is legal everywhere below (in place); any other overlap is an error.
+ *
+ * The GPU method is the device-scale form of the paper's cache-friendly
+ * two-pass scheme (Section 2.2): every tile of the input is loaded once into
+ * registers, scanned there (the wavefront scan is the 64-lane analogue of the
+ * horizontal in-register scan of Section 3.1), and written once, while the
+ * carry between tiles travels through a chain of per-tile status words in
+ * which each tile waits only on its predecessors (the adjacent-only
+ * synchronisation that Section 2.2.1 suggests in place of a central barrier).
+ * HBM traffic is therefore the two-words-per-element floor: 8 bytes per
+ * element for every entry point, plus 8 bytes per tile of status.
+ *
+ * Conventions for every function:
+ *  - Pointers named in/out/grad_* and offsets are DEVICE pointers owned by the
+ *    caller; they must stay valid until the work enqueued on `stream`
+ *    completes.  Elements need 4-byte alignment, offsets 8-byte alignment;
+ *    16-byte aligned buffers take the vector fast path automatically.
+ *  - All functions are asynchronous on `stream` (a hipStream_t; 0 = the null
+ *    stream) and do not synchronise the host, except where a workspace has to
+ *    grow (see scan_reserve).
+ *  - Argument errors are detected on the host and returned before anything is
+ *    enqueued.  n == 0 is a successful no-op.  Malformed offsets CONTENTS
+ *    (device data) are not checked: the kernels never read or write outside
+ *    in[0..n), out[0..n), offsets[0..S], but the results are then unspecified.
+ *  - No function aborts or throws across the ABI; a failing HIP call is
+ *    reported as SCAN_ERROR_LAUNCH / SCAN_ERROR_OUT_OF_MEMORY and its hipError_t
+ *    is kept for scan_last_hip_error().
+ *  - Integer scans wrap modulo 2^32; int32 and uint32 give identical bits.
+ *  - float32 scans: the result is within 2^-20 * sum_{j<=i} |a_j| of the exact
+ *    prefix sum (sum_{j<i} for exclusive).  The paper notes that parallel float
+ *    sums may differ slightly from sequential ones; this library fixes the
+ *    summation order per tuning configuration, so repeated runs give identical
+ *    bits.
+ *  - Concurrency: each stream gets its own workspace; calls on one stream run
+ *    in stream order.  Two host threads may call concurrently on different
+ *    streams.
+ */
+#ifndef MI355SCAN_H
+#define MI355SCAN_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SCAN_SUCCESS = 0,
+    SCAN_ERROR_INVALID_VALUE = 1,   /* bad pointer, size, alignment, flag or dtype */
+    SCAN_ERROR_OVERLAP = 2,         /* in and out overlap without being equal */
+    SCAN_ERROR_OUT_OF_MEMORY = 3,   /* workspace allocation failed */
+    SCAN_ERROR_LAUNCH = 4,          /* a HIP call failed (see scan_last_hip_error) */
+    SCAN_ERROR_NOT_SUPPORTED = 5,   /* no gfx950 device, or unsupported combination */
+    SCAN_ERROR_CAPTURE = 6,         /* would allocate while the stream is being captured */
+    SCAN_ERROR_TIMEOUT = 7          /* a device-side wait hit its spin limit */
+} scan_status_t;
+
+typedef enum { SCAN_I32 = 0, SCAN_U32 = 1, SCAN_F32 = 2 } scan_dtype_t;
+
+/* Flag bits. */
+#define SCAN_EXCLUSIVE 0x1u  /* exclusive scan (identity first)              */
+#define SCAN_REVERSE   0x2u  /* suffix scan: out[i] = a[i] + ... + a[n-1]     */
+
+/* ---- flat scans (Introduction: definition; Section 2: in place or not) ----
+ * in, out: device arrays of n elements (in == out allowed).  n >= 0. */
+scan_status_t scan_inclusive_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t stream);
+scan_status_t scan_inclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t stream);
+scan_status_t scan_inclusive_f32(const float *in, float *out, int64_t n, hipStream_t stream);
+scan_status_t scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t stream);
+scan_status_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t stream);
+scan_status_t scan_exclusive_f32(const float *in, float *out, int64_t n, hipStream_t stream);
+
+/* General flat scan: any dtype, flags = SCAN_EXCLUSIVE | SCAN_REVERSE. */
+scan_status_t scan_flat(const void *in, void *out, int64_t n, scan_dtype_t dtype,
+                        uint32_t flags, hipStream_t stream);
+
+/* ---- batched segmented scan (one persistent launch) ----
+ * Scans num_segments independent segments of one concatenated array: segment
+ * s covers in[offsets[s] .. offsets[s+1]), and each segment's result is the
+ * flat scan of that segment alone (the running total restarts at every
+ * segment start; exclusive results are 0 at a segment's first element).
+ * This is the histogram-to-offsets use of the Introduction done for many
+ * histograms at once.
+ * offsets: device int64[num_segments + 1], offsets[0] = 0, non-decreasing,
+ * offsets[num_segments] = n; empty segments allowed.  num_segments >= 1 when
+ * n > 0.  Enqueues two kernels (a tile-to-segment map and the scan). */
+scan_status_t scan_segmented_batch(const void *in, void *out, const int64_t *offsets,
+                                   int32_t num_segments, int64_t n, scan_dtype_t dtype,
+                                   uint32_t flags, hipStream_t stream);
+
+/* ---- float32 cumsum backward ----
+ * For y = inclusive cumsum of x (per segment if offsets != NULL), the
+ * gradient is the suffix sum of the upstream gradient:
+ *     grad_in[i] = sum_{j >= i, j in the same segment} grad_out[j].
+ * offsets may be NULL (one segment of length n; num_segments ignored).
+ * grad_in == grad_out is allowed. */
+scan_status_t scan_f32_backward(const float *grad_out, float *grad_in, int64_t n,
+                                const int64_t *offsets, int32_t num_segments,
+                                hipStream_t stream);
+
+/* ---- workspace ----
+ * Each stream owns a workspace (tile status words and counters) that is
+ * allocated on first use and grown when a larger n arrives; growing
+ * synchronises the stream and is refused during stream capture.  Call
+ * scan_reserve(max_n) before capturing library calls into a graph.
+ * The workspace keeps itself clean between launches (no reset kernel or
+ * memset is needed per call). */
+scan_status_t scan_reserve(int64_t max_n, hipStream_t stream);
+scan_status_t scan_release(hipStream_t stream);   /* synchronises the stream */
+
+/* ---- graphs ----
+ * Capture a batched segmented scan (both kernels) into a hipGraph with its own
+ * workspace; replay it with scan_graph_launch (on any stream; replays of one
+ * graph must not overlap in time).  The buffers are bound at creation: the
+ * caller may change their contents between replays but not their addresses. */
+scan_status_t scan_segmented_graph_create(const void *in, void *out, const int64_t *offsets,
+                                          int32_t num_segments, int64_t n, scan_dtype_t dtype,
+                                          uint32_t flags, hipStream_t stream, void **graph);
+/* Comparator: one flat-scan launch per segment (host_offsets: HOST int64[S+1]),
+ * captured into one graph; replay with scan_graph_launch. */
+scan_status_t scan_looped_graph_create(const void *in, void *out, const int64_t *host_offsets,
+                                       int32_t num_segments, scan_dtype_t dtype,
+                                       uint32_t flags, hipStream_t stream, void **graph);
+scan_status_t scan_graph_launch(void *graph, hipStream_t stream);
+scan_status_t scan_graph_destroy(void *graph);
+
+/* Comparator: one flat-scan launch per segment, enqueued eagerly from the
+ * host (host_offsets: HOST int64[S+1]).  Results equal scan_segmented_batch. */
+scan_status_t scan_segmented_looped(const void *in, void *out, const int64_t *host_offsets,
+                                    int32_t num_segments, scan_dtype_t dtype,
+                                    uint32_t flags, hipStream_t stream);
+
+/* ---- tuning ----
+ * Kernel configurations are numbered 0 .. scan_num_configs()-1; each fixes the
+ * workgroup size, the elements per thread (tile = threads * items; the tile is
+ * the GPU counterpart of the paper's cache-sized partition, Section 2.2, whose
+ * size the paper tunes in Section 4.2.4), non-temporal memory hints and
+ * persistence.  A tuning table maps (dtype, flags, segmented, log2 n bucket)
+ * to a configuration; built-in defaults can be replaced from a JSON file. */
+int32_t       scan_num_configs(void);
+scan_status_t scan_config_info(int32_t config, int32_t *block, int32_t *items,
+                               int32_t *nontemporal, int32_t *persistent);
+/* Force a configuration for subsequent calls (-1 = use the tuning table). */
+scan_status_t scan_force_config(int32_t config);
+/* Configuration the table selects for a call of this shape. */
+int32_t       scan_selected_config(scan_dtype_t dtype, uint32_t flags, int32_t segmented, int64_t n);
+/* Time every configuration on the caller's buffers (in, out: n elements;
+ * offsets/num_segments for segmented, else NULL/0), store the fastest in the
+ * table for n's bucket and return it in *best (may be NULL).  Synchronises. */
+scan_status_t scan_autotune(const void *in, void *out, int64_t n, const int64_t *offsets,
+                            int32_t num_segments, scan_dtype_t dtype, uint32_t flags,
+                            int32_t reps, hipStream_t stream, int32_t *best);
+scan_status_t scan_tune_save(const char *path);
+scan_status_t scan_tune_load(const char *path);
+
+/* ---- diagnostics ---- */
+const char   *scan_status_string(scan_status_t status);
+int32_t       scan_last_hip_error(void);
+/* Spin limit for device-side waits (iterations; 0 restores the default).  A
+ * wait that exceeds it gives up, marks the workspace's error word and lets the
+ * kernel finish (the results of that call are then invalid). */
+scan_status_t scan_set_spin_limit(uint32_t limit);
+/* Synchronise `stream`, read and clear the device error word of its
+ * workspace: SCAN_SUCCESS or SCAN_ERROR_TIMEOUT. */
+scan_status_t scan_check_device_error(hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MI355SCAN_H */

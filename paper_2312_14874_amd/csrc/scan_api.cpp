@@ -1,0 +1,769 @@
+// Host side of the C ABI declared in include/mi355scan.h: argument checks,
+// per-stream workspaces, configuration dispatch, launches, graphs and the
+// autotuner.  Every step of the scan itself runs in the HIP kernels of
+// scan_kernels.hip; this file only prepares launches.
+#include <hip/hip_runtime.h>
+
+#include <dlfcn.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/mi355scan.h"
+#include "scan_shared.hpp"
+#include "scan_table.hpp"
+#include "validate.hpp"
+
+namespace mi355scan {
+namespace {
+
+constexpr uint32_t kDefaultSpinLimit = 1u << 20;   // about a second of sleeping polls
+constexpr int kDefaultFlatConfig = 2;               // 512 threads x 16 items, one tile per workgroup
+constexpr int kDefaultSegConfig = 12;               // 512 threads x 16 items, persistent
+constexpr int kBuckets = 64;
+
+thread_local int t_last_hip = 0;
+std::mutex g_mu;
+uint32_t g_spin_limit = kDefaultSpinLimit;
+int g_forced = -1;
+int g_table[2][2][kBuckets];      // [int / f32][segmented][floor(log2 n)] -> config, -1 = default
+
+scan_status_t st(int s) { return static_cast<scan_status_t>(s); }
+
+scan_status_t hip_fail(hipError_t e, scan_status_t code = SCAN_ERROR_LAUNCH) {
+  t_last_hip = (int)e;
+  return code;
+}
+
+int bucket_of(int64_t n) {
+  int b = 0;
+  while (b < kBuckets - 1 && (int64_t(1) << (b + 1)) <= n) ++b;
+  return b;
+}
+
+int opclass_of(scan_dtype_t dt) { return dt == SCAN_F32 ? 1 : 0; }
+
+// ------------------------------------------------------------------ devices
+struct DeviceInfo {
+  bool supported = false;
+  int cus = 0;
+};
+std::map<int, DeviceInfo> g_devices;
+
+scan_status_t current_device(int *dev, DeviceInfo *info) {
+  hipError_t e = hipGetDevice(dev);
+  if (e != hipSuccess) return hip_fail(e, SCAN_ERROR_NOT_SUPPORTED);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_devices.find(*dev);
+  if (it == g_devices.end()) {
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, *dev);
+    if (e != hipSuccess) return hip_fail(e, SCAN_ERROR_NOT_SUPPORTED);
+    DeviceInfo di;
+    di.supported = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    di.cus = prop.multiProcessorCount;
+    it = g_devices.emplace(*dev, di).first;
+  }
+  *info = it->second;
+  return info->supported ? SCAN_SUCCESS : SCAN_ERROR_NOT_SUPPORTED;
+}
+
+// --------------------------------------------------------------- workspaces
+// Layout of one allocation: header (64 B) | status[2][capacity] (u64) |
+// tile map[capacity + 1] (u32).
+struct Workspace {
+  int device = -1;
+  char *base = nullptr;
+  WsHeader *hdr = nullptr;
+  uint64_t *status = nullptr;
+  uint32_t *map = nullptr;
+  int64_t capacity = 0;   // tiles
+};
+
+size_t ws_bytes(int64_t cap) {
+  return sizeof(WsHeader) + (size_t)cap * 2 * sizeof(uint64_t) + (size_t)(cap + 1) * sizeof(uint32_t);
+}
+
+scan_status_t ws_alloc(Workspace *w, int device, int64_t cap, hipStream_t stream) {
+  const size_t bytes = ws_bytes(cap);
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return hip_fail(e, SCAN_ERROR_OUT_OF_MEMORY);
+  e = hipMemsetAsync(p, 0, bytes, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    (void)hipFree(p);
+    return hip_fail(e);
+  }
+  w->device = device;
+  w->base = static_cast<char *>(p);
+  w->hdr = reinterpret_cast<WsHeader *>(w->base);
+  w->status = reinterpret_cast<uint64_t *>(w->base + sizeof(WsHeader));
+  w->map = reinterpret_cast<uint32_t *>(w->base + sizeof(WsHeader) + (size_t)cap * 2 * sizeof(uint64_t));
+  w->capacity = cap;
+  return SCAN_SUCCESS;
+}
+
+void ws_free(Workspace *w) {
+  if (w->base) (void)hipFree(w->base);
+  *w = Workspace();
+}
+
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+int64_t min_tile() {
+  int64_t m = INT64_MAX;
+  for (int i = 0; i < kNumShapes; ++i) m = std::min<int64_t>(m, (int64_t)kShapes[i].block * kShapes[i].items);
+  return m;
+}
+
+int64_t tiles_for(int64_t n, int64_t tile) { return (n + tile - 1) / tile; }
+
+scan_status_t stream_ws(int device, hipStream_t stream, int64_t need, Workspace **out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  Workspace &w = g_ws[std::make_pair(device, stream)];
+  if (w.base && w.capacity >= need) {
+    *out = &w;
+    return SCAN_SUCCESS;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(stream, &cs);
+  if (e != hipSuccess) return hip_fail(e);
+  if (cs != hipStreamCaptureStatusNone) return SCAN_ERROR_CAPTURE;
+  const int64_t cap = std::max<int64_t>({need, 2 * w.capacity, 1024});
+  if (w.base) {
+    e = hipStreamSynchronize(stream);   // the old workspace may still be in use
+    if (e != hipSuccess) return hip_fail(e);
+    ws_free(&w);
+  }
+  scan_status_t s = ws_alloc(&w, device, cap, stream);
+  if (s != SCAN_SUCCESS) return s;
+  *out = &w;
+  return SCAN_SUCCESS;
+}
+
+// ---------------------------------------------------------------- tuning
+void load_default_tune_file();
+
+std::once_flag g_init_once;
+
+void ensure_init() {
+  std::call_once(g_init_once, [] {
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      for (auto &a : g_table)
+        for (auto &b : a)
+          for (int &c : b) c = -1;
+    }
+    load_default_tune_file();
+  });
+}
+
+int select_config(int opclass, bool seg, int64_t n) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_forced >= 0) return g_forced;
+  const int c = g_table[opclass][seg ? 1 : 0][bucket_of(n)];
+  if (c >= 0 && c < kNumConfigs) return c;
+  return seg ? kDefaultSegConfig : kDefaultFlatConfig;
+}
+
+std::map<const void *, int> g_occupancy;
+
+int resident_blocks(const void *fn, int block, int cus) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_occupancy.find(fn);
+    if (it != g_occupancy.end()) return it->second * cus;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_occupancy[fn] = per_cu;
+  return per_cu * cus;
+}
+
+// ---------------------------------------------------------------- launching
+struct Call {
+  const void *in;
+  void *out;
+  int64_t n;
+  int opclass;
+  bool seg;
+  uint32_t flags;
+  const int64_t *offsets;
+  int64_t num_segments;
+};
+
+// Tiles a call of this shape needs under configuration cfg.
+int64_t call_tiles(const Call &c, int cfg) {
+  const KernelShape &sh = kShapes[kConfigs[cfg].shape];
+  return tiles_for(c.n, (int64_t)sh.block * sh.items);
+}
+
+// Enqueue one scan (plus the tile map for segmented calls).  ws_override is a
+// graph-owned workspace (already large enough) or null for the stream's own.
+scan_status_t launch(const Call &c, hipStream_t stream, Workspace *ws_override, int cfg_override) {
+  if (c.n == 0) return SCAN_SUCCESS;
+  int dev = 0;
+  DeviceInfo di;
+  scan_status_t s = current_device(&dev, &di);
+  if (s != SCAN_SUCCESS) return s;
+  const int cfg = cfg_override >= 0 ? cfg_override : select_config(c.opclass, c.seg, c.n);
+  const Config &cf = kConfigs[cfg];
+  const KernelShape &sh = kShapes[cf.shape];
+  const int64_t tile = (int64_t)sh.block * sh.items;
+  const int64_t T = tiles_for(c.n, tile);
+  const void *fn = sh.fn[c.opclass][c.seg ? 1 : 0];
+
+  Workspace *ws = nullptr;
+  if (T > 1) {
+    if (ws_override) {
+      if (ws_override->capacity < T) return SCAN_ERROR_INVALID_VALUE;
+      ws = ws_override;
+    } else {
+      s = stream_ws(dev, stream, T, &ws);
+      if (s != SCAN_SUCCESS) return s;
+    }
+  }
+
+  KernelArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.in = c.in;
+  a.out = c.out;
+  a.n = c.n;
+  a.tiles = T;
+  a.hdr = ws ? ws->hdr : nullptr;
+  a.status = ws ? ws->status : nullptr;
+  a.capacity = ws ? ws->capacity : 0;
+  a.offsets = c.offsets;
+  a.tile_seg = nullptr;
+  a.num_segments = c.num_segments;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    a.spin_limit = g_spin_limit;
+  }
+  a.exclusive = (c.flags & SCAN_EXCLUSIVE) ? 1u : 0u;
+  a.reverse = (c.flags & SCAN_REVERSE) ? 1u : 0u;
+  a.vec_in = ((uintptr_t)c.in & 15u) == 0;
+  a.vec_out = ((uintptr_t)c.out & 15u) == 0;
+
+  int64_t grid = T;
+  if (cf.persistent && T > 1) grid = std::min<int64_t>(T, resident_blocks(fn, sh.block, di.cus));
+  a.one_tile = grid == T ? 1u : 0u;
+  a.total_acquires = a.one_tile ? (uint64_t)T : (uint64_t)(T + grid);
+
+  if (c.seg && T > 1) {
+    const int64_t cnt = T + 1;
+    const int mb = 256;
+    const int64_t mgrid = (cnt + mb - 1) / mb;
+    const int64_t *off = c.offsets;
+    int64_t S = c.num_segments;
+    int64_t tl = tile;
+    int32_t shift = a.reverse ? 1 : 0;
+    uint32_t *map = ws->map;
+    void *margs[] = {&off, &S, &tl, (void *)&T, &shift, &map};
+    hipError_t e = hipLaunchKernel(kTileSegmentMap, dim3((unsigned)mgrid), dim3(mb), margs, 0, stream);
+    if (e != hipSuccess) return hip_fail(e);
+    a.tile_seg = ws->map;
+  }
+  void *kargs[] = {&a};
+  hipError_t e = hipLaunchKernel(fn, dim3((unsigned)grid), dim3(sh.block), kargs, 0, stream);
+  if (e != hipSuccess) return hip_fail(e);
+  return SCAN_SUCCESS;
+}
+
+scan_status_t flat(const void *in, void *out, int64_t n, scan_dtype_t dt, uint32_t flags,
+                   hipStream_t stream) {
+  int r = check_dtype((int)dt);
+  if (r == kOk) r = check_flags(flags);
+  if (r == kOk) r = check_flat(in, out, n);
+  if (r != kOk) return st(r);
+  if (n == 0) return SCAN_SUCCESS;
+  ensure_init();
+  Call c{in, out, n, opclass_of(dt), false, flags, nullptr, 0};
+  return launch(c, stream, nullptr, -1);
+}
+
+scan_status_t segmented(const void *in, void *out, const int64_t *offsets, int32_t S, int64_t n,
+                        scan_dtype_t dt, uint32_t flags, hipStream_t stream, Workspace *ws, int cfg) {
+  int r = check_dtype((int)dt);
+  if (r == kOk) r = check_flags(flags);
+  if (r == kOk) r = check_segmented(in, out, offsets, S, n);
+  if (r != kOk) return st(r);
+  if (n == 0) return SCAN_SUCCESS;
+  ensure_init();
+  Call c{in, out, n, opclass_of(dt), true, flags, offsets, S};
+  return launch(c, stream, ws, cfg);
+}
+
+// Per-segment launches (comparator).  host_offsets are host memory.
+scan_status_t looped(const void *in, void *out, const int64_t *host_offsets, int32_t S,
+                     scan_dtype_t dt, uint32_t flags, hipStream_t stream, Workspace *ws) {
+  int r = check_dtype((int)dt);
+  if (r == kOk) r = check_flags(flags);
+  if (r != kOk) return st(r);
+  if (S < 0 || (S > 0 && !host_offsets)) return SCAN_ERROR_INVALID_VALUE;
+  if (S == 0) return SCAN_SUCCESS;
+  const int64_t n = host_offsets[S];
+  if (host_offsets[0] != 0) return SCAN_ERROR_INVALID_VALUE;
+  for (int32_t s = 0; s < S; ++s)
+    if (host_offsets[s + 1] < host_offsets[s]) return SCAN_ERROR_INVALID_VALUE;
+  r = check_flat(in, out, n);
+  if (r != kOk) return st(r);
+  ensure_init();
+  const char *pi = static_cast<const char *>(in);
+  char *po = static_cast<char *>(out);
+  for (int32_t s = 0; s < S; ++s) {
+    const int64_t lo = host_offsets[s], len = host_offsets[s + 1] - lo;
+    if (len == 0) continue;
+    Call c{pi + 4 * lo, po + 4 * lo, len, opclass_of(dt), false, flags, nullptr, 0};
+    scan_status_t e = launch(c, stream, ws, -1);
+    if (e != SCAN_SUCCESS) return e;
+  }
+  return SCAN_SUCCESS;
+}
+
+// ---------------------------------------------------------------- graphs
+struct GraphObj {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  Workspace ws;
+};
+
+template <class Enqueue>
+scan_status_t capture(int64_t need_tiles, hipStream_t stream, Enqueue enqueue, void **out) {
+  if (!out) return SCAN_ERROR_INVALID_VALUE;
+  *out = nullptr;
+  int dev = 0;
+  DeviceInfo di;
+  scan_status_t s = current_device(&dev, &di);
+  if (s != SCAN_SUCCESS) return s;
+  GraphObj *g = new GraphObj();
+  s = ws_alloc(&g->ws, dev, std::max<int64_t>(need_tiles, 2), stream);
+  if (s != SCAN_SUCCESS) {
+    delete g;
+    return s;
+  }
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    ws_free(&g->ws);
+    delete g;
+    return hip_fail(e);
+  }
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    s = enqueue(cs, &g->ws);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (s == SCAN_SUCCESS && e2 != hipSuccess) s = hip_fail(e2);
+    g->graph = graph;
+    if (s == SCAN_SUCCESS) {
+      e2 = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+      if (e2 != hipSuccess) s = hip_fail(e2);
+    }
+  } else {
+    s = hip_fail(e);
+  }
+  (void)hipStreamDestroy(cs);
+  if (s != SCAN_SUCCESS) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    ws_free(&g->ws);
+    delete g;
+    return s;
+  }
+  *out = g;
+  return SCAN_SUCCESS;
+}
+
+// ---------------------------------------------------------------- tune file
+std::string default_tune_path() {
+  const char *env = std::getenv("MI355SCAN_TUNE_FILE");
+  if (env && *env) return env;
+  Dl_info info;
+  if (dladdr((void *)&default_tune_path, &info) && info.dli_fname) {
+    std::string so = info.dli_fname;
+    const size_t slash = so.rfind('/');
+    const std::string dir = slash == std::string::npos ? "." : so.substr(0, slash);
+    return dir + "/tune/gfx950.json";
+  }
+  return "";
+}
+
+// Reads the integer after "key": inside [b, e); returns false if absent.
+bool json_int(const std::string &s, size_t b, size_t e, const char *key, long *out) {
+  const std::string k = std::string("\"") + key + "\"";
+  size_t p = s.find(k, b);
+  if (p == std::string::npos || p >= e) return false;
+  p = s.find(':', p + k.size());
+  if (p == std::string::npos || p >= e) return false;
+  ++p;
+  while (p < e && (s[p] == ' ' || s[p] == '\t')) ++p;
+  char *end = nullptr;
+  const long v = std::strtol(s.c_str() + p, &end, 10);
+  if (end == s.c_str() + p) return false;
+  *out = v;
+  return true;
+}
+
+bool json_str(const std::string &s, size_t b, size_t e, const char *key, std::string *out) {
+  const std::string k = std::string("\"") + key + "\"";
+  size_t p = s.find(k, b);
+  if (p == std::string::npos || p >= e) return false;
+  p = s.find('"', s.find(':', p + k.size()));
+  if (p == std::string::npos || p >= e) return false;
+  const size_t q = s.find('"', p + 1);
+  if (q == std::string::npos || q >= e) return false;
+  *out = s.substr(p + 1, q - p - 1);
+  return true;
+}
+
+// Each entry: {"op": "int"|"f32", "segmented": 0|1, "log2n": b, "config": c,
+// "block": B, "items": I}; entries whose block/items disagree with config c of
+// this build are ignored.
+scan_status_t parse_tune(const std::string &text) {
+  int table[2][2][kBuckets];
+  for (auto &a : table)
+    for (auto &b : a)
+      for (int &c : b) c = -1;
+  size_t pos = text.find("\"entries\"");
+  if (pos == std::string::npos) return SCAN_ERROR_INVALID_VALUE;
+  for (;;) {
+    const size_t b = text.find('{', pos);
+    if (b == std::string::npos) break;
+    const size_t e = text.find('}', b);
+    if (e == std::string::npos) break;
+    pos = e + 1;
+    std::string op;
+    long seg = 0, bucket = 0, cfg = 0, block = 0, items = 0;
+    if (!json_str(text, b, e, "op", &op) || !json_int(text, b, e, "segmented", &seg) ||
+        !json_int(text, b, e, "log2n", &bucket) || !json_int(text, b, e, "config", &cfg) ||
+        !json_int(text, b, e, "block", &block) || !json_int(text, b, e, "items", &items))
+      continue;
+    if (cfg < 0 || cfg >= kNumConfigs || bucket < 0 || bucket >= kBuckets) continue;
+    const KernelShape &sh = kShapes[kConfigs[cfg].shape];
+    if (sh.block != block || sh.items != items) continue;
+    const int oc = op == "f32" ? 1 : (op == "int" ? 0 : -1);
+    if (oc < 0) continue;
+    table[oc][seg ? 1 : 0][bucket] = (int)cfg;
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  std::memcpy(g_table, table, sizeof(table));
+  return SCAN_SUCCESS;
+}
+
+scan_status_t load_tune(const char *path) {
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return SCAN_ERROR_INVALID_VALUE;
+  std::string text;
+  char buf[4096];
+  size_t k;
+  while ((k = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, k);
+  std::fclose(f);
+  return parse_tune(text);
+}
+
+void load_default_tune_file() {
+  const std::string p = default_tune_path();
+  if (!p.empty()) (void)load_tune(p.c_str());
+}
+
+}  // namespace
+}  // namespace mi355scan
+
+using namespace mi355scan;
+
+extern "C" {
+
+scan_status_t scan_flat(const void *in, void *out, int64_t n, scan_dtype_t dtype, uint32_t flags,
+                        hipStream_t stream) {
+  return flat(in, out, n, dtype, flags, stream);
+}
+
+scan_status_t scan_inclusive_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s) {
+  return flat(in, out, n, SCAN_I32, 0u, s);
+}
+scan_status_t scan_inclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t s) {
+  return flat(in, out, n, SCAN_U32, 0u, s);
+}
+scan_status_t scan_inclusive_f32(const float *in, float *out, int64_t n, hipStream_t s) {
+  return flat(in, out, n, SCAN_F32, 0u, s);
+}
+scan_status_t scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s) {
+  return flat(in, out, n, SCAN_I32, SCAN_EXCLUSIVE, s);
+}
+scan_status_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t s) {
+  return flat(in, out, n, SCAN_U32, SCAN_EXCLUSIVE, s);
+}
+scan_status_t scan_exclusive_f32(const float *in, float *out, int64_t n, hipStream_t s) {
+  return flat(in, out, n, SCAN_F32, SCAN_EXCLUSIVE, s);
+}
+
+scan_status_t scan_segmented_batch(const void *in, void *out, const int64_t *offsets,
+                                   int32_t num_segments, int64_t n, scan_dtype_t dtype,
+                                   uint32_t flags, hipStream_t stream) {
+  return segmented(in, out, offsets, num_segments, n, dtype, flags, stream, nullptr, -1);
+}
+
+scan_status_t scan_f32_backward(const float *grad_out, float *grad_in, int64_t n,
+                                const int64_t *offsets, int32_t num_segments, hipStream_t stream) {
+  if (!offsets) return flat(grad_out, grad_in, n, SCAN_F32, SCAN_REVERSE, stream);
+  return segmented(grad_out, grad_in, offsets, num_segments, n, SCAN_F32, SCAN_REVERSE, stream,
+                   nullptr, -1);
+}
+
+scan_status_t scan_reserve(int64_t max_n, hipStream_t stream) {
+  if (max_n < 0) return SCAN_ERROR_INVALID_VALUE;
+  if (max_n == 0) return SCAN_SUCCESS;
+  ensure_init();
+  int dev = 0;
+  DeviceInfo di;
+  scan_status_t s = current_device(&dev, &di);
+  if (s != SCAN_SUCCESS) return s;
+  Workspace *w = nullptr;
+  return stream_ws(dev, stream, tiles_for(max_n, min_tile()), &w);
+}
+
+scan_status_t scan_release(hipStream_t stream) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, SCAN_ERROR_NOT_SUPPORTED);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_ws.find(std::make_pair(dev, stream));
+  if (it == g_ws.end()) return SCAN_SUCCESS;
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e);
+  ws_free(&it->second);
+  g_ws.erase(it);
+  return SCAN_SUCCESS;
+}
+
+scan_status_t scan_segmented_graph_create(const void *in, void *out, const int64_t *offsets,
+                                          int32_t num_segments, int64_t n, scan_dtype_t dtype,
+                                          uint32_t flags, hipStream_t stream, void **graph) {
+  int r = check_dtype((int)dtype);
+  if (r == kOk) r = check_flags(flags);
+  if (r == kOk) r = check_segmented(in, out, offsets, num_segments, n);
+  if (r != kOk) return st(r);
+  ensure_init();
+  const int cfg = select_config(opclass_of(dtype), true, n);
+  Call c{in, out, n, opclass_of(dtype), true, flags, offsets, num_segments};
+  const int64_t need = call_tiles(c, cfg);
+  return capture(need, stream,
+                 [&](hipStream_t cs, Workspace *ws) {
+                   return segmented(in, out, offsets, num_segments, n, dtype, flags, cs, ws, cfg);
+                 },
+                 graph);
+}
+
+scan_status_t scan_looped_graph_create(const void *in, void *out, const int64_t *host_offsets,
+                                       int32_t num_segments, scan_dtype_t dtype, uint32_t flags,
+                                       hipStream_t stream, void **graph) {
+  if (num_segments < 0 || (num_segments > 0 && !host_offsets)) return SCAN_ERROR_INVALID_VALUE;
+  ensure_init();
+  int64_t need = 2;
+  for (int32_t s = 0; s < num_segments; ++s) {
+    const int64_t len = host_offsets[s + 1] - host_offsets[s];
+    if (len > 0) {
+      Call c{in, out, len, opclass_of(dtype), false, flags, nullptr, 0};
+      need = std::max(need, call_tiles(c, select_config(c.opclass, false, len)));
+    }
+  }
+  return capture(need, stream,
+                 [&](hipStream_t cs, Workspace *ws) {
+                   return looped(in, out, host_offsets, num_segments, dtype, flags, cs, ws);
+                 },
+                 graph);
+}
+
+scan_status_t scan_graph_launch(void *graph, hipStream_t stream) {
+  if (!graph) return SCAN_ERROR_INVALID_VALUE;
+  GraphObj *g = static_cast<GraphObj *>(graph);
+  hipError_t e = hipGraphLaunch(g->exec, stream);
+  return e == hipSuccess ? SCAN_SUCCESS : hip_fail(e);
+}
+
+scan_status_t scan_graph_destroy(void *graph) {
+  if (!graph) return SCAN_ERROR_INVALID_VALUE;
+  GraphObj *g = static_cast<GraphObj *>(graph);
+  (void)hipDeviceSynchronize();
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  ws_free(&g->ws);
+  delete g;
+  return SCAN_SUCCESS;
+}
+
+scan_status_t scan_segmented_looped(const void *in, void *out, const int64_t *host_offsets,
+                                    int32_t num_segments, scan_dtype_t dtype, uint32_t flags,
+                                    hipStream_t stream) {
+  return looped(in, out, host_offsets, num_segments, dtype, flags, stream, nullptr);
+}
+
+int32_t scan_num_configs(void) { return kNumConfigs; }
+
+scan_status_t scan_config_info(int32_t config, int32_t *block, int32_t *items, int32_t *nontemporal,
+                               int32_t *persistent) {
+  if (config < 0 || config >= kNumConfigs) return SCAN_ERROR_INVALID_VALUE;
+  const KernelShape &sh = kShapes[kConfigs[config].shape];
+  if (block) *block = sh.block;
+  if (items) *items = sh.items;
+  if (nontemporal) *nontemporal = sh.nontemporal;
+  if (persistent) *persistent = kConfigs[config].persistent;
+  return SCAN_SUCCESS;
+}
+
+scan_status_t scan_force_config(int32_t config) {
+  if (config < -1 || config >= kNumConfigs) return SCAN_ERROR_INVALID_VALUE;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_forced = config;
+  return SCAN_SUCCESS;
+}
+
+int32_t scan_selected_config(scan_dtype_t dtype, uint32_t flags, int32_t segmented, int64_t n) {
+  (void)flags;
+  if (check_dtype((int)dtype) != kOk || n < 0) return -1;
+  ensure_init();
+  return select_config(opclass_of(dtype), segmented != 0, n);
+}
+
+scan_status_t scan_autotune(const void *in, void *out, int64_t n, const int64_t *offsets,
+                            int32_t num_segments, scan_dtype_t dtype, uint32_t flags, int32_t reps,
+                            hipStream_t stream, int32_t *best) {
+  int r = check_dtype((int)dtype);
+  if (r == kOk) r = check_flags(flags);
+  const bool seg = offsets != nullptr;
+  if (r == kOk) r = seg ? check_segmented(in, out, offsets, num_segments, n) : check_flat(in, out, n);
+  if (r != kOk) return st(r);
+  if (n == 0 || reps < 1) return SCAN_ERROR_INVALID_VALUE;
+  ensure_init();
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e != hipSuccess) return hip_fail(e);
+  e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(e);
+  }
+  Call c{in, out, n, opclass_of(dtype), seg, flags, offsets, num_segments};
+  float best_ms = 1e30f;
+  int best_cfg = -1;
+  scan_status_t s = SCAN_SUCCESS;
+  for (int cfg = 0; cfg < kNumConfigs && s == SCAN_SUCCESS; ++cfg) {
+    std::vector<float> times;
+    for (int i = 0; i < reps + 1 && s == SCAN_SUCCESS; ++i) {
+      if ((e = hipEventRecord(e0, stream)) != hipSuccess) { s = hip_fail(e); break; }
+      s = launch(c, stream, nullptr, cfg);
+      if (s != SCAN_SUCCESS) break;
+      if ((e = hipEventRecord(e1, stream)) != hipSuccess) { s = hip_fail(e); break; }
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) { s = hip_fail(e); break; }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (i > 0) times.push_back(ms);   // first run warms up
+    }
+    if (s != SCAN_SUCCESS) break;
+    std::sort(times.begin(), times.end());
+    const float med = times[times.size() / 2];
+    if (med < best_ms) {
+      best_ms = med;
+      best_cfg = cfg;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != SCAN_SUCCESS) return s;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table[c.opclass][seg ? 1 : 0][bucket_of(n)] = best_cfg;
+  }
+  if (best) *best = best_cfg;
+  return SCAN_SUCCESS;
+}
+
+scan_status_t scan_tune_save(const char *path) {
+  if (!path) return SCAN_ERROR_INVALID_VALUE;
+  ensure_init();
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return SCAN_ERROR_INVALID_VALUE;
+  std::fprintf(f, "{\n  \"arch\": \"gfx950\",\n  \"format\": 1,\n  \"entries\": [");
+  bool first = true;
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (int oc = 0; oc < 2; ++oc)
+    for (int sg = 0; sg < 2; ++sg)
+      for (int b = 0; b < kBuckets; ++b) {
+        const int cfg = g_table[oc][sg][b];
+        if (cfg < 0) continue;
+        const KernelShape &sh = kShapes[kConfigs[cfg].shape];
+        std::fprintf(f,
+                     "%s\n    {\"op\": \"%s\", \"segmented\": %d, \"log2n\": %d, \"config\": %d, "
+                     "\"block\": %d, \"items\": %d, \"nontemporal\": %d, \"persistent\": %d}",
+                     first ? "" : ",", oc ? "f32" : "int", sg, b, cfg, sh.block, sh.items,
+                     sh.nontemporal, kConfigs[cfg].persistent);
+        first = false;
+      }
+  std::fprintf(f, "\n  ]\n}\n");
+  std::fclose(f);
+  return SCAN_SUCCESS;
+}
+
+scan_status_t scan_tune_load(const char *path) {
+  if (!path) return SCAN_ERROR_INVALID_VALUE;
+  ensure_init();
+  return load_tune(path);
+}
+
+const char *scan_status_string(scan_status_t status) {
+  switch (status) {
+    case SCAN_SUCCESS: return "success";
+    case SCAN_ERROR_INVALID_VALUE: return "invalid value";
+    case SCAN_ERROR_OVERLAP: return "input and output overlap without being equal";
+    case SCAN_ERROR_OUT_OF_MEMORY: return "out of device memory";
+    case SCAN_ERROR_LAUNCH: return "HIP call failed";
+    case SCAN_ERROR_NOT_SUPPORTED: return "no supported (gfx950) device";
+    case SCAN_ERROR_CAPTURE: return "workspace growth refused during stream capture";
+    case SCAN_ERROR_TIMEOUT: return "device wait exceeded its spin limit";
+  }
+  return "unknown status";
+}
+
+int32_t scan_last_hip_error(void) { return t_last_hip; }
+
+scan_status_t scan_set_spin_limit(uint32_t limit) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_spin_limit = limit ? limit : kDefaultSpinLimit;
+  return SCAN_SUCCESS;
+}
+
+scan_status_t scan_check_device_error(hipStream_t stream) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, SCAN_ERROR_NOT_SUPPORTED);
+  WsHeader *hdr = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_ws.find(std::make_pair(dev, stream));
+    if (it != g_ws.end()) hdr = it->second.hdr;
+  }
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e);
+  if (!hdr) return SCAN_SUCCESS;
+  uint32_t err = 0;
+  e = hipMemcpy(&err, &hdr->error, sizeof(err), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e);
+  if (!err) return SCAN_SUCCESS;
+  const uint32_t zero = 0;
+  e = hipMemcpy(&hdr->error, &zero, sizeof(zero), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e);
+  return SCAN_ERROR_TIMEOUT;
+}
+
+}  // extern "C"

@@ -1,0 +1,51 @@
+// Types shared by the kernels and the host launcher: the tile status word
+// encoding, the workspace header and the kernel argument block.
+#pragma once
+#include <stdint.h>
+
+namespace mi355scan {
+
+// ----------------------------------------------------------------- status words
+// A tile's status is one 64-bit word holding a 2-state flag and its value, so a
+// single relaxed agent-scope atomic load or store moves both together; no
+// fences are needed (nothing else is published through it).
+constexpr uint32_t kEmpty = 0;   // nothing published yet
+constexpr uint32_t kAgg = 1;     // value = this tile's own aggregate
+constexpr uint32_t kPrefix = 2;  // value = inclusive prefix through this tile
+
+// Workspace header (device memory, zeroed once at allocation).  Two status
+// arrays alternate between launches: a launch uses array `parity` and cleans
+// array 1-parity, which the previous launch left dirty on [0, dirty[1-parity]).
+// The workgroup that performs the launch's last counter increment flips the
+// parity; by then every workgroup of the launch has read it.  So no memset or
+// reset kernel is needed between launches, also inside graphs.
+struct alignas(64) WsHeader {
+  uint32_t parity;
+  uint32_t error;        // set when a wait exceeds its spin limit
+  uint64_t dirty[2];     // words of status array q that may be non-zero
+  uint64_t counter[2];   // tile counters, one per status array
+  uint64_t reserved[2];
+};
+static_assert(sizeof(WsHeader) == 64, "header layout");
+
+struct KernelArgs {
+  const void *in;
+  void *out;
+  int64_t n;
+  int64_t tiles;              // number of tiles T
+  uint64_t total_acquires;    // counter increments of this launch
+  WsHeader *hdr;              // null when tiles == 1
+  uint64_t *status;           // 2 * capacity words
+  int64_t capacity;           // words per status array
+  const int64_t *offsets;     // segmented: S+1 CSR offsets
+  const uint32_t *tile_seg;   // segmented: first segment per tile boundary (T+1), or null if T == 1
+  int64_t num_segments;
+  uint32_t spin_limit;
+  uint32_t exclusive;
+  uint32_t reverse;
+  uint32_t vec_in;            // in is 16-byte aligned
+  uint32_t vec_out;           // out is 16-byte aligned
+  uint32_t one_tile;          // every workgroup takes exactly one tile
+};
+
+}  // namespace mi355scan

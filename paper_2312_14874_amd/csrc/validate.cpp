@@ -1,0 +1,33 @@
+#include "validate.hpp"
+
+namespace mi355scan {
+
+int check_dtype(int dtype) { return (dtype >= 0 && dtype <= 2) ? kOk : kInvalid; }
+
+int check_flags(uint32_t flags) { return (flags & ~kKnownFlags) ? kInvalid : kOk; }
+
+int check_flat(const void *in, const void *out, int64_t n) {
+  if (n < 0) return kInvalid;
+  if (n == 0) return kOk;
+  if (!in || !out) return kInvalid;
+  const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
+  if ((a & 3u) || (b & 3u)) return kInvalid;
+  if (n > (int64_t)(UINTPTR_MAX / 8)) return kInvalid;
+  const uintptr_t bytes = (uintptr_t)n * 4u;
+  if (a + bytes < a || b + bytes < b) return kInvalid;   // address wrap
+  if (a != b && a < b + bytes && b < a + bytes) return kOverlap;
+  return kOk;
+}
+
+int check_segmented(const void *in, const void *out, const void *offsets,
+                    int64_t num_segments, int64_t n) {
+  if (num_segments < 0) return kInvalid;
+  const int r = check_flat(in, out, n);
+  if (r != kOk) return r;
+  if (n == 0) return kOk;
+  if (num_segments == 0) return kInvalid;     // offsets[S] = n > 0 needs a segment
+  if (!offsets || ((uintptr_t)offsets & 7u)) return kInvalid;
+  return kOk;
+}
+
+}  // namespace mi355scan

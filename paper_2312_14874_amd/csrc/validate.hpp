@@ -1,0 +1,27 @@
+// Host-side argument validation for the C ABI.  No HIP calls: every check
+// here runs before anything is enqueued, and can be tested without a GPU.
+#pragma once
+#include <stdint.h>
+
+namespace mi355scan {
+
+// Mirrors scan_status_t.
+enum Status : int {
+  kOk = 0, kInvalid = 1, kOverlap = 2, kOom = 3, kLaunch = 4,
+  kNotSupported = 5, kCapture = 6, kTimeout = 7
+};
+
+constexpr uint32_t kFlagExclusive = 0x1u;
+constexpr uint32_t kFlagReverse = 0x2u;
+constexpr uint32_t kKnownFlags = kFlagExclusive | kFlagReverse;
+
+// dtype: 0 = i32, 1 = u32, 2 = f32
+int check_dtype(int dtype);
+int check_flags(uint32_t flags);
+// in/out arrays of n 4-byte elements; in == out allowed, other overlap refused
+int check_flat(const void *in, const void *out, int64_t n);
+// segmented batch: offsets (S+1 int64, 8-byte aligned) required when n > 0
+int check_segmented(const void *in, const void *out, const void *offsets,
+                    int64_t num_segments, int64_t n);
+
+}  // namespace mi355scan

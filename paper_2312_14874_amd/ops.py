@@ -1,0 +1,254 @@
+"""torch-facing wrappers: validate tensors, then call the C ABI.
+
+torch supplies device memory and the stream (torch.cuda.current_stream());
+every step of the scan runs in the HIP kernels of libmi355scan.so.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._lib import (SCAN_EXCLUSIVE, SCAN_F32, SCAN_I32, SCAN_REVERSE, SCAN_U32,
+                   check, lib)
+
+_DTYPES = {torch.int32: SCAN_I32, torch.float32: SCAN_F32}
+if hasattr(torch, "uint32"):
+    _DTYPES[torch.uint32] = SCAN_U32
+
+
+def _stream(dev: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _flags(exclusive: bool, reverse: bool) -> int:
+    return (SCAN_EXCLUSIVE if exclusive else 0) | (SCAN_REVERSE if reverse else 0)
+
+
+def _check_tensor(x: torch.Tensor, name: str) -> int:
+    if not isinstance(x, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if not x.is_cuda:
+        raise ValueError("%s must be a GPU tensor" % name)
+    if x.dtype not in _DTYPES:
+        raise TypeError("%s: unsupported dtype %s (int32, uint32, float32)" % (name, x.dtype))
+    if not x.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return _DTYPES[x.dtype]
+
+
+def _out_like(x: torch.Tensor, out):
+    if out is None:
+        return torch.empty_like(x)
+    if out.dtype != x.dtype or out.numel() != x.numel() or out.device != x.device or not out.is_contiguous():
+        raise ValueError("out must be a contiguous tensor with the input's dtype, size and device")
+    return out
+
+
+def _check_offsets(offsets: torch.Tensor, x: torch.Tensor) -> int:
+    if offsets.dtype != torch.int64 or offsets.dim() != 1 or not offsets.is_contiguous():
+        raise TypeError("offsets must be a contiguous 1-D int64 tensor")
+    if offsets.device != x.device:
+        raise ValueError("offsets must be on the input's device")
+    if offsets.numel() < 1:
+        raise ValueError("offsets needs num_segments + 1 entries")
+    return offsets.numel() - 1
+
+
+def cumsum(x: torch.Tensor, exclusive: bool = False, reverse: bool = False, out=None) -> torch.Tensor:
+    """Scan of a contiguous int32 / uint32 / float32 GPU tensor (flattened).
+
+    out may be x itself (in place)."""
+    dt = _check_tensor(x, "x")
+    out = _out_like(x, out)
+    with torch.cuda.device(x.device):
+        check(lib.scan_flat(x.data_ptr(), out.data_ptr(), x.numel(), dt,
+                            _flags(exclusive, reverse), _stream(x.device)), "scan_flat")
+    return out
+
+
+def exclusive_cumsum(x: torch.Tensor, out=None) -> torch.Tensor:
+    return cumsum(x, exclusive=True, out=out)
+
+
+def segmented_scan(x: torch.Tensor, offsets: torch.Tensor, exclusive: bool = False,
+                   reverse: bool = False, out=None) -> torch.Tensor:
+    """Independent scans of the segments x[offsets[s]:offsets[s+1]] in one launch."""
+    dt = _check_tensor(x, "x")
+    S = _check_offsets(offsets, x)
+    out = _out_like(x, out)
+    with torch.cuda.device(x.device):
+        check(lib.scan_segmented_batch(x.data_ptr(), out.data_ptr(), offsets.data_ptr(), S,
+                                       x.numel(), dt, _flags(exclusive, reverse),
+                                       _stream(x.device)), "scan_segmented_batch")
+    return out
+
+
+def segmented_scan_looped(x: torch.Tensor, host_offsets, exclusive: bool = False,
+                          reverse: bool = False, out=None) -> torch.Tensor:
+    """Comparator: one flat-scan launch per segment (host_offsets on the CPU)."""
+    import numpy as np
+    dt = _check_tensor(x, "x")
+    off = np.ascontiguousarray(np.asarray(host_offsets, dtype=np.int64))
+    out = _out_like(x, out)
+    with torch.cuda.device(x.device):
+        check(lib.scan_segmented_looped(x.data_ptr(), out.data_ptr(), off.ctypes.data, off.size - 1,
+                                        dt, _flags(exclusive, reverse), _stream(x.device)),
+              "scan_segmented_looped")
+    return out
+
+
+def cumsum_backward(grad: torch.Tensor, offsets=None, out=None) -> torch.Tensor:
+    """Gradient of an inclusive float32 cumsum: per-segment suffix sums of grad."""
+    if _check_tensor(grad, "grad") != SCAN_F32:
+        raise TypeError("cumsum_backward takes float32")
+    out = _out_like(grad, out)
+    with torch.cuda.device(grad.device):
+        if offsets is None:
+            check(lib.scan_f32_backward(grad.data_ptr(), out.data_ptr(), grad.numel(), None, 0,
+                                        _stream(grad.device)), "scan_f32_backward")
+        else:
+            S = _check_offsets(offsets, grad)
+            check(lib.scan_f32_backward(grad.data_ptr(), out.data_ptr(), grad.numel(),
+                                        offsets.data_ptr(), S, _stream(grad.device)),
+                  "scan_f32_backward")
+    return out
+
+
+class CumsumFn(torch.autograd.Function):
+    """Differentiable float32 inclusive cumsum over a flat tensor or over the
+    ragged rows given by CSR offsets.  The backward is the reverse (suffix)
+    scan; nothing but the offsets is saved, because the map is linear."""
+
+    @staticmethod
+    def forward(ctx, x, offsets=None):
+        if x.dtype != torch.float32:
+            raise TypeError("CumsumFn takes float32")
+        xc = x.contiguous()
+        y = cumsum(xc) if offsets is None else segmented_scan(xc, offsets)
+        ctx.offsets = offsets
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        return cumsum_backward(gy.contiguous(), ctx.offsets), None
+
+
+def cumsum_autograd(x: torch.Tensor, offsets=None) -> torch.Tensor:
+    return CumsumFn.apply(x, offsets)
+
+
+class SegmentedScanGraph:
+    """A batched segmented scan captured once into a hipGraph and replayed.
+
+    The tensors are bound at construction; change their contents, not their
+    storage, between replays."""
+
+    def __init__(self, x: torch.Tensor, out: torch.Tensor, offsets: torch.Tensor,
+                 exclusive: bool = False, reverse: bool = False):
+        dt = _check_tensor(x, "x")
+        S = _check_offsets(offsets, x)
+        _out_like(x, out)
+        self._keep = (x, out, offsets)
+        self.device = x.device
+        h = ctypes.c_void_p()
+        with torch.cuda.device(x.device):
+            check(lib.scan_segmented_graph_create(x.data_ptr(), out.data_ptr(), offsets.data_ptr(), S,
+                                                  x.numel(), dt, _flags(exclusive, reverse),
+                                                  _stream(x.device), ctypes.byref(h)),
+                  "scan_segmented_graph_create")
+        self._h = h
+
+    def launch(self):
+        with torch.cuda.device(self.device):
+            check(lib.scan_graph_launch(self._h, _stream(self.device)), "scan_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            with torch.cuda.device(self.device):
+                lib.scan_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class LoopedScanGraph(SegmentedScanGraph):
+    """Comparator: one flat-scan launch per segment, captured into one graph."""
+
+    def __init__(self, x: torch.Tensor, out: torch.Tensor, host_offsets,
+                 exclusive: bool = False, reverse: bool = False):
+        import numpy as np
+        dt = _check_tensor(x, "x")
+        _out_like(x, out)
+        off = np.ascontiguousarray(np.asarray(host_offsets, dtype=np.int64))
+        self._keep = (x, out, off)
+        self.device = x.device
+        h = ctypes.c_void_p()
+        with torch.cuda.device(x.device):
+            check(lib.scan_looped_graph_create(x.data_ptr(), out.data_ptr(), off.ctypes.data,
+                                               off.size - 1, dt, _flags(exclusive, reverse),
+                                               _stream(x.device), ctypes.byref(h)),
+                  "scan_looped_graph_create")
+        self._h = h
+
+
+def num_configs() -> int:
+    return lib.scan_num_configs()
+
+
+def config_info(cfg: int) -> dict:
+    b, i, nt, p = (ctypes.c_int32() for _ in range(4))
+    check(lib.scan_config_info(cfg, ctypes.byref(b), ctypes.byref(i), ctypes.byref(nt), ctypes.byref(p)))
+    return {"config": cfg, "block": b.value, "items": i.value, "nontemporal": nt.value,
+            "persistent": p.value, "tile": b.value * i.value}
+
+
+def force_config(cfg: int = -1) -> None:
+    check(lib.scan_force_config(cfg), "scan_force_config")
+
+
+def selected_config(dtype: torch.dtype, n: int, segmented: bool = False, flags: int = 0) -> int:
+    return lib.scan_selected_config(_DTYPES[dtype], flags, int(segmented), n)
+
+
+def autotune(x: torch.Tensor, out: torch.Tensor, offsets=None, exclusive: bool = False,
+             reverse: bool = False, reps: int = 5) -> int:
+    dt = _check_tensor(x, "x")
+    best = ctypes.c_int32(-1)
+    off_ptr, S = None, 0
+    if offsets is not None:
+        S = _check_offsets(offsets, x)
+        off_ptr = offsets.data_ptr()
+    with torch.cuda.device(x.device):
+        check(lib.scan_autotune(x.data_ptr(), out.data_ptr(), x.numel(), off_ptr, S, dt,
+                                _flags(exclusive, reverse), reps, _stream(x.device),
+                                ctypes.byref(best)), "scan_autotune")
+    return best.value
+
+
+def tune_save(path: str) -> None:
+    check(lib.scan_tune_save(path.encode()), "scan_tune_save")
+
+
+def tune_load(path: str) -> None:
+    check(lib.scan_tune_load(path.encode()), "scan_tune_load")
+
+
+def reserve(max_n: int, device=None) -> None:
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    with torch.cuda.device(dev):
+        check(lib.scan_reserve(max_n, _stream(dev)), "scan_reserve")
+
+
+def set_spin_limit(limit: int) -> None:
+    check(lib.scan_set_spin_limit(limit), "scan_set_spin_limit")
+
+
+def check_device_error(device=None) -> int:
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    with torch.cuda.device(dev):
+        return lib.scan_check_device_error(_stream(dev))

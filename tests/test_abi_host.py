@@ -1,0 +1,125 @@
+"""C ABI on the host: the library loads, exports every declared entry point,
+and rejects bad arguments before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mi355scan.h")
+
+
+def _lib():
+    from paper_2312_14874_amd import _lib as L
+    return L
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(scan_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = _lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(L.lib, name), name
+        assert name in L.SIGNATURES, "binding lacks " + name
+
+
+def test_status_strings():
+    L = _lib()
+    for code in range(8):
+        s = L.lib.scan_status_string(code)
+        assert s and s != b"unknown status"
+    assert L.lib.scan_status_string(99) == b"unknown status"
+
+
+INVALID, OVERLAP = 1, 2
+
+
+@pytest.mark.parametrize("args,code", [
+    ((None, None, 10, 0, 0), INVALID),          # null pointers
+    ((4096, 8192, -1, 0, 0), INVALID),          # n < 0
+    ((4096, 8192, 10, 3, 0), INVALID),          # unknown dtype
+    ((4096, 8192, 10, 0, 4), INVALID),          # unknown flag
+    ((4098, 8192, 10, 0, 0), INVALID),          # misaligned (needs 4 bytes)
+    ((4096, 4100, 10, 0, 0), OVERLAP),          # partial overlap
+    ((4100, 4096, 10, 2, 1), OVERLAP),
+])
+def test_flat_argument_errors(args, code):
+    L = _lib()
+    assert L.lib.scan_flat(*args, None) == code
+
+
+def test_zero_length_is_noop():
+    L = _lib()
+    assert L.lib.scan_flat(None, None, 0, 0, 0, None) == 0
+    assert L.lib.scan_inclusive_i32(None, None, 0, None) == 0
+    assert L.lib.scan_segmented_batch(None, None, None, 0, 0, 0, 0, None) == 0
+
+
+def test_segmented_argument_errors():
+    L = _lib()
+    f = L.lib.scan_segmented_batch
+    assert f(4096, 8192, None, 3, 10, 0, 0, None) == INVALID        # no offsets
+    assert f(4096, 8192, 16, -1, 10, 0, 0, None) == INVALID         # S < 0
+    assert f(4096, 8192, 16, 0, 10, 0, 0, None) == INVALID          # S = 0 with n > 0
+    assert f(4096, 8192, 20, 3, 10, 0, 0, None) == INVALID          # offsets misaligned
+    assert f(4096, 4100, 16, 3, 10, 0, 0, None) == OVERLAP
+
+
+def test_other_argument_errors():
+    L = _lib()
+    assert L.lib.scan_reserve(-1, None) == INVALID
+    assert L.lib.scan_reserve(0, None) == 0
+    assert L.lib.scan_graph_launch(None, None) == INVALID
+    assert L.lib.scan_graph_destroy(None) == INVALID
+    assert L.lib.scan_force_config(10_000) == INVALID
+    assert L.lib.scan_config_info(-1, None, None, None, None) == INVALID
+    assert L.lib.scan_segmented_looped(4096, 8192, None, 2, 0, 0, None) == INVALID
+    h = ctypes.c_void_p()
+    assert L.lib.scan_looped_graph_create(4096, 8192, None, 2, 0, 0, None, ctypes.byref(h)) == INVALID
+
+
+def test_configs_are_well_formed():
+    from paper_2312_14874_amd import config_info, num_configs
+    n = num_configs()
+    assert n >= 10
+    for c in range(n):
+        info = config_info(c)
+        assert info["block"] % 64 == 0 and info["items"] % 4 == 0
+        assert 2048 <= info["tile"] <= 32768
+
+
+def test_tune_file_roundtrip(tmp_path):
+    from paper_2312_14874_amd import config_info, force_config, lib, selected_config, tune_load, tune_save
+    import torch
+    p = tmp_path / "t.json"
+    info = config_info(5)
+    p.write_text('{"arch": "gfx950", "entries": [{"op": "int", "segmented": 0, "log2n": 20, '
+                 '"config": 5, "block": %d, "items": %d}, '
+                 '{"op": "f32", "segmented": 1, "log2n": 21, "config": 5, "block": 1, "items": 1}]}'
+                 % (info["block"], info["items"]))
+    tune_load(str(p))
+    assert selected_config(torch.int32, 1 << 20) == 5
+    assert selected_config(torch.int32, (1 << 21) - 1) == 5
+    # mismatching block/items are ignored
+    assert selected_config(torch.float32, 1 << 21, segmented=True) != 5
+    tune_save(str(tmp_path / "u.json"))
+    assert '"config": 5' in (tmp_path / "u.json").read_text()
+    force_config(3)
+    assert selected_config(torch.int32, 1 << 20) == 3
+    force_config(-1)
+    # restore the shipped table
+    from paper_2312_14874_amd import _lib as L
+    shipped = os.path.join(os.path.dirname(L.LIB_PATH), "tune", "gfx950.json")
+    if os.path.exists(shipped):
+        tune_load(shipped)
+    else:
+        p.write_text('{"entries": []}')
+        tune_load(str(p))
+    assert lib.scan_tune_load(str(tmp_path / "missing.json").encode()) == INVALID

@@ -1,0 +1,58 @@
+"""Batched segmented scans (one launch) against the oracle's per-segment
+scans, and against per-segment launches of the flat scan."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import assert_f32_close, configs, first_mismatch, segmented
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("cfg", range(20))
+def test_int_random_offsets_every_config(cfg):
+    g = np.random.default_rng(100 + cfg)
+    tile = configs()[cfg]["tile"]
+    for n, S in ((1, 1), (300, 7), (tile + 5, 40), (9 * tile + 17, 3), (40 * tile + 1, 900)):
+        a = workloads.full_u32(n, seed=n + cfg)
+        off = workloads.random_offsets(g, n, S)
+        for ex in (False, True):
+            for rev in (False, True):
+                got = segmented(a, off, exclusive=ex, reverse=rev, cfg=cfg)
+                want = oracle.segmented_int(a, off, exclusive=ex, reverse=rev)
+                msg = first_mismatch(got, want)
+                assert not msg, "cfg %d n %d S %d ex %d rev %d: %s" % (cfg, n, S, ex, rev, msg)
+
+
+@pytest.mark.parametrize("cfg", [2, 12, 0, 14])
+def test_f32_segments(cfg):
+    g = np.random.default_rng(cfg)
+    tile = configs()[cfg]["tile"]
+    n = 25 * tile + 333
+    a = workloads.normal_f32(n, seed=cfg)
+    off = workloads.random_offsets(g, n, 60)
+    for ex in (False, True):
+        for rev in (False, True):
+            got = segmented(a, off, exclusive=ex, reverse=rev, cfg=cfg)
+            ref, ab = oracle.segmented_f32(a, off, exclusive=ex, reverse=rev)
+            assert_f32_close(got, ref, ab, "cfg %d ex %d rev %d" % (cfg, ex, rev))
+
+
+def test_special_segmentations():
+    n = 100_003
+    a = workloads.full_u32(n, seed=3)
+    # one segment == flat scan
+    for ex in (False, True):
+        assert not first_mismatch(segmented(a, np.array([0, n]), exclusive=ex),
+                                  oracle.scan_int(a, exclusive=ex))
+    # all length-1 segments
+    off = np.arange(n + 1, dtype=np.int64)
+    assert not first_mismatch(segmented(a, off), a)
+    assert not first_mismatch(segmented(a, off, exclusive=True), np.zeros(n, dtype=np.uint32))
+    # many empty segments, including leading and trailing ones
+    off = np.array([0, 0, 0, 10, 10, 5000, 5000, n, n, n], dtype=np.int64)
+    for ex in (False, True):
+        for rev in (False, True):
+            assert not first_mismatch(segmented(a, off, exclusive=ex, reverse=rev),
+                                      oracle.segmented_int(a, off, exclusive=ex, reverse=rev))
