@@ -1,0 +1,292 @@
+"""Benchmark: single-pass int32/uint32 inclusive scan at n = 2^28 on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+A step is one inclusive scan of n = 2^28 full-range uint32 values (wrapping
+modulo 2^32; int32 is the same kernel on the same bits), out of place, inputs
+resident in HBM.  Prints ONE JSON line on stdout; progress goes to stderr.
+
+  value      whole-job throughput in GB/s of algorithmic traffic (8 bytes per
+             element: one 4-byte read and one 4-byte write), from the wall
+             clock of the K timed steps
+  roofline   the scan kernel's average duration from HIP events on the stream
+             it runs on, against the 8 TB/s HBM peak; `traffic` is the HBM
+             bytes per launch measured with rocprofv3 counters (profiles/),
+             or null when the kernel sources changed since that measurement
+  cpu_baseline  the sequential oracle on one host core, over repeated passes
+             of the same 2^28-element input (about 10 s)
+  segmented  the batched segmented scan (4096 segments, log-uniform lengths in
+             [1, 2^20], Poisson(8) int32 counts, exclusive, one persistent
+             launch replayed from a hipGraph) against one flat-scan launch per
+             segment, eager and graph-captured; all results are compared
+Extra modes (not the headline line): --n, --dtype f32, --copy-calibration.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scan_u32_n2p28_traffic.txt")
+KERNEL_SOURCES = ["paper_2312_14874_amd/csrc/scan_device.hpp", "paper_2312_14874_amd/csrc/scan_shared.hpp",
+                  "paper_2312_14874_amd/csrc/scan_kernels.hip"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n: int):
+    """HBM bytes per launch from the committed counter summary, or None if it
+    does not match the current kernel sources or this n."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if "=" in line and not line.startswith("#"):
+                    k, v = line.split("=", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_sha") != kernel_source_sha() or int(kv.get("n", -1)) != n:
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--n", type=int, default=1 << 28)
+    p.add_argument("--dtype", choices=["u32", "f32"], default="u32")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    p.add_argument("--no-segmented", action="store_true", help="skip the segmented comparison")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="run only plain device copies of the scan's bytes (counter calibration)")
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads
+    import paper_2312_14874_amd as scan
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    n = args.n
+    props = torch.cuda.get_device_properties(dev)
+    log("device:", props.name, getattr(props, "gcnArchName", ""), "CUs", props.multi_processor_count)
+
+    if args.copy_calibration:
+        # plain copies of exactly the scan's per-launch bytes: n*4 read, n*4 written
+        x = torch.empty(n, dtype=torch.int32, device=dev).random_()
+        y = torch.empty_like(x)
+        for _ in range(args.warmup + args.steps):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        log("copy: %d bytes read + %d written per launch, %.1f us, %.1f GB/s"
+            % (4 * n, 4 * n, ms * 1e3, 8 * n / (ms * 1e-3) / 1e9))
+        return
+
+    # ---------------------------------------------------------- input, resident in HBM
+    t0 = time.time()
+    if args.dtype == "u32":
+        a = workloads.full_u32(n)
+        x = torch.from_numpy(a.view(np.int32)).to(dev)
+        dtype_code, dtype_name = scan.SCAN_U32, "u32"
+    else:
+        a = workloads.normal_f32(n)
+        x = torch.from_numpy(a).to(dev)
+        dtype_code, dtype_name = scan.SCAN_F32, "f32"
+    y = torch.empty_like(x)
+    log("input ready (%.1f s)" % (time.time() - t0))
+    stream = torch.cuda.current_stream(dev)
+    sptr = __import__("ctypes").c_void_p(stream.cuda_stream)
+
+    def step():
+        s = scan.lib.scan_flat(x.data_ptr(), y.data_ptr(), n, dtype_code, 0, sptr)
+        if s != 0:
+            raise scan.ScanError(s, "scan_flat")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # ---------------------------------------------------------- timed region
+    K = args.steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for i in range(K):
+        ev[i][0].record(stream)
+        step()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    kern_ms = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    kern_avg_ms = sum(kern_ms) / K
+    ms_per_step = wall * 1e3 / K
+    alg_bytes = 8.0 * n
+    value = alg_bytes / (ms_per_step * 1e-3) / 1e9
+    achieved = alg_bytes / (kern_avg_ms * 1e-3) / 1e9
+    log("scan: %.1f us/step wall, kernel avg %.1f us (p10 %.1f, p90 %.1f), %.1f GB/s"
+        % (ms_per_step * 1e3, kern_avg_ms * 1e3, kern_ms[K // 10] * 1e3, kern_ms[(9 * K) // 10] * 1e3, achieved))
+
+    # ---------------------------------------------------------- parity of the timed output
+    import oracle
+    got = y.cpu().numpy()
+    if args.dtype == "u32":
+        want = oracle.scan_int(a)
+        parity = "bit-exact" if np.array_equal(got.view(np.uint32), want) else "MISMATCH"
+    else:
+        ref, ab = oracle.scan_f32(a)
+        ok = np.all(np.abs(got.astype(np.float64) - ref) <= np.ldexp(ab, -20))
+        parity = "within 2^-20*sum|a|" if ok else "MISMATCH"
+    log("parity:", parity)
+
+    # ---------------------------------------------------------- CPU oracle baseline
+    cpu = None
+    if not args.no_cpu:
+        reps, total, times = 0, 0.0, []
+        while total < 10.0 and reps < 100:
+            c0 = time.perf_counter()
+            oracle.scan_int(a) if args.dtype == "u32" else oracle.scan_f32(a, with_abs=False)
+            dt = time.perf_counter() - c0
+            times.append(dt)
+            total += dt
+            reps += 1
+        times.sort()
+        med = times[len(times) // 2]
+        cpu = {"value": round(alg_bytes / med / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": "%d sequential passes over the same n=2^%d input (%.1f s), median pass %.3f s = %.3f Gelem/s"
+                         % (reps, n.bit_length() - 1, total, med, n / med / 1e9)}
+        log("cpu oracle:", cpu["value"], "GB/s")
+
+    # ---------------------------------------------------------- segmented vs per-launch
+    seg = None
+    if not args.no_segmented and args.dtype == "u32":
+        seg = segmented_comparison(scan, torch, np, workloads, oracle, dev)
+
+    del x, y
+    traffic = measured_traffic(n) if args.dtype == "u32" else None
+    out = {
+        "metric": "int32 scan GB/s at n=2^28 vs HBM peak; batched-segmented vs per-launch",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype_name,
+        "data": "synthetic",
+        "config": {"workload": "inclusive scan, n=2^%d %s (%s), out of place, single pass"
+                               % (n.bit_length() - 1, "uint32 full-range, wrapping" if args.dtype == "u32"
+                                  else "float32 normal(0,1)", "seed %d" % (1002 if args.dtype == "u32" else 1003)),
+                   "n": n, "scan_config": scan.selected_config(torch.int32 if args.dtype == "u32" else torch.float32, n),
+                   "parity": parity},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_GBS, 4), "traffic": traffic,
+                     "kernel_avg_us": round(kern_avg_ms * 1e3, 2), "algorithmic_bytes": int(alg_bytes)},
+        "cpu_baseline": cpu,
+        "segmented": seg,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def segmented_comparison(scan, torch, np, workloads, oracle, dev):
+    """Batched segmented scan (graph replay) vs one launch per segment."""
+    import ctypes
+    t0 = time.time()
+    vals, off = workloads.segments()
+    n = int(off[-1])
+    S = off.size - 1
+    x = torch.from_numpy(vals).to(dev)
+    offs = torch.from_numpy(off).to(dev)
+    y_b = torch.empty_like(x)
+    y_l = torch.empty_like(x)
+    y_g = torch.empty_like(x)
+    log("segments ready: S=%d n=%d (%.1f s)" % (S, n, time.time() - t0))
+    stream = torch.cuda.current_stream(dev)
+    sptr = ctypes.c_void_p(stream.cuda_stream)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ts.sort()
+        return ts[len(ts) // 2]
+
+    g_batched = scan.SegmentedScanGraph(x, y_b, offs, exclusive=True)
+    t_batched = timed(g_batched.launch, 20)
+    t_batched_eager = timed(lambda: scan.segmented_scan(x, offs, exclusive=True, out=y_b), 20)
+    t_looped = timed(lambda: scan.check(scan.lib.scan_segmented_looped(
+        x.data_ptr(), y_l.data_ptr(), off.ctypes.data, S, scan.SCAN_I32, scan.SCAN_EXCLUSIVE, sptr)), 5)
+    g_looped = scan.LoopedScanGraph(x, y_g, off, exclusive=True)
+    t_looped_graph = timed(g_looped.launch, 5)
+    g_batched.launch()
+    torch.cuda.synchronize()
+    want = oracle.segmented_int(vals, off, exclusive=True)
+    ok_b = np.array_equal(y_b.cpu().numpy(), want)
+    ok_l = np.array_equal(y_l.cpu().numpy(), want)
+    ok_g = np.array_equal(y_g.cpu().numpy(), want)
+    g_batched.close()
+    g_looped.close()
+    alg = 8.0 * n + 8.0 * (S + 1)
+    res = {
+        "workload": "exclusive per-segment scan, S=%d, n=%d int32 Poisson(8), lengths log-uniform [1,2^20] (seed 1004)" % (S, n),
+        "batched_graph_us": round(t_batched * 1e3, 1),
+        "batched_eager_us": round(t_batched_eager * 1e3, 1),
+        "per_launch_eager_us": round(t_looped * 1e3, 1),
+        "per_launch_graph_us": round(t_looped_graph * 1e3, 1),
+        "speedup_vs_eager": round(t_looped / t_batched, 2),
+        "speedup_vs_graph": round(t_looped_graph / t_batched, 2),
+        "batched_GBps": round(alg / (t_batched * 1e-3) / 1e9, 1),
+        "results_equal": bool(ok_b and ok_l and ok_g),
+    }
+    log("segmented:", res)
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -145,11 +145,16 @@ scan_status_t scan_segmented_looped(const void *in, void *out, const int64_t *ho
  * workgroup size, the elements per thread (tile = threads * items; the tile is
  * the GPU counterpart of the paper's cache-sized partition, Section 2.2, whose
  * size the paper tunes in Section 4.2.4), non-temporal memory hints and
- * persistence.  A tuning table maps (dtype, flags, segmented, log2 n bucket)
+ * how tiles are assigned to workgroups.  A tuning table maps (dtype, flags, segmented, log2 n bucket)
  * to a configuration; built-in defaults can be replaced from a JSON file. */
 int32_t       scan_num_configs(void);
+/* mode: 0 = one tile per workgroup, tile numbers from a device counter;
+ *       1 = persistent grid taking tiles from the counter;
+ *       2 = tile number = workgroup index (no counter; relies on workgroups
+ *           being dispatched in index order, bounded by the spin limit);
+ *       4 = static round robin over a cooperatively launched resident grid. */
 scan_status_t scan_config_info(int32_t config, int32_t *block, int32_t *items,
-                               int32_t *nontemporal, int32_t *persistent);
+                               int32_t *nontemporal, int32_t *mode);
 /* Force a configuration for subsequent calls (-1 = use the tuning table). */
 scan_status_t scan_force_config(int32_t config);
 /* Configuration the table selects for a call of this shape. */

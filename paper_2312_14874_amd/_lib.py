@@ -8,6 +8,11 @@ from __future__ import annotations
 import ctypes
 import os
 
+# torch ships its own HIP runtime with the same soname as /opt/rocm's.  Import
+# it first so the library below binds to the runtime torch already uses: two
+# HIP runtimes in one process would not share devices, streams or memory.
+import torch  # noqa: F401
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmi355scan.so")
 

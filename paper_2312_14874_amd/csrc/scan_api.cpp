@@ -24,9 +24,11 @@
 namespace mi355scan {
 namespace {
 
-constexpr uint32_t kDefaultSpinLimit = 1u << 20;   // about a second of sleeping polls
-constexpr int kDefaultFlatConfig = 2;               // 512 threads x 16 items, one tile per workgroup
-constexpr int kDefaultSegConfig = 12;               // 512 threads x 16 items, persistent
+// A legitimate wait never outlasts the whole kernel (about a millisecond at
+// 2^30 elements); 2^16 sleeping polls is of the order of 0.1 s.
+constexpr uint32_t kDefaultSpinLimit = 1u << 16;
+constexpr int kDefaultFlatConfig = 6;               // 256 threads x 128 items, resident grid
+constexpr int kDefaultSegConfig = 2;                // 256 threads x 64 items, tile = workgroup index
 constexpr int kBuckets = 64;
 
 thread_local int t_last_hip = 0;
@@ -76,19 +78,22 @@ scan_status_t current_device(int *dev, DeviceInfo *info) {
 }
 
 // --------------------------------------------------------------- workspaces
-// Layout of one allocation: header (64 B) | status[2][capacity] (u64) |
-// tile map[capacity + 1] (u32).
+// Layout of one allocation: header (64 B) | publish counters (kPubWords u64) |
+// status[2][capacity] (u64) | tile map[capacity + 1] (u32).
 struct Workspace {
   int device = -1;
   char *base = nullptr;
   WsHeader *hdr = nullptr;
+  uint64_t *pubcnt = nullptr;
   uint64_t *status = nullptr;
   uint32_t *map = nullptr;
   int64_t capacity = 0;   // tiles
 };
 
+constexpr size_t kStatusOffset = sizeof(WsHeader) + kPubWords * sizeof(uint64_t);
+
 size_t ws_bytes(int64_t cap) {
-  return sizeof(WsHeader) + (size_t)cap * 2 * sizeof(uint64_t) + (size_t)(cap + 1) * sizeof(uint32_t);
+  return kStatusOffset + (size_t)cap * 2 * sizeof(uint64_t) + (size_t)(cap + 1) * sizeof(uint32_t);
 }
 
 scan_status_t ws_alloc(Workspace *w, int device, int64_t cap, hipStream_t stream) {
@@ -105,8 +110,9 @@ scan_status_t ws_alloc(Workspace *w, int device, int64_t cap, hipStream_t stream
   w->device = device;
   w->base = static_cast<char *>(p);
   w->hdr = reinterpret_cast<WsHeader *>(w->base);
-  w->status = reinterpret_cast<uint64_t *>(w->base + sizeof(WsHeader));
-  w->map = reinterpret_cast<uint32_t *>(w->base + sizeof(WsHeader) + (size_t)cap * 2 * sizeof(uint64_t));
+  w->pubcnt = reinterpret_cast<uint64_t *>(w->base + sizeof(WsHeader));
+  w->status = reinterpret_cast<uint64_t *>(w->base + kStatusOffset);
+  w->map = reinterpret_cast<uint32_t *>(w->base + kStatusOffset + (size_t)cap * 2 * sizeof(uint64_t));
   w->capacity = cap;
   return SCAN_SUCCESS;
 }
@@ -221,7 +227,7 @@ scan_status_t launch(const Call &c, hipStream_t stream, Workspace *ws_override, 
   const KernelShape &sh = kShapes[cf.shape];
   const int64_t tile = (int64_t)sh.block * sh.items;
   const int64_t T = tiles_for(c.n, tile);
-  const void *fn = sh.fn[c.opclass][c.seg ? 1 : 0];
+  const void *fn = sh.fn[c.opclass][c.seg ? 1 : 0][(c.flags & SCAN_REVERSE) ? 1 : 0];
 
   Workspace *ws = nullptr;
   if (T > 1) {
@@ -255,11 +261,28 @@ scan_status_t launch(const Call &c, hipStream_t stream, Workspace *ws_override, 
   a.vec_in = ((uintptr_t)c.in & 15u) == 0;
   a.vec_out = ((uintptr_t)c.out & 15u) == 0;
 
+  const int threads = sh.block;
   int64_t grid = T;
-  if (cf.persistent && T > 1) grid = std::min<int64_t>(T, resident_blocks(fn, sh.block, di.cus));
-  a.one_tile = grid == T ? 1u : 0u;
-  a.total_acquires = a.one_tile ? (uint64_t)T : (uint64_t)(T + grid);
-
+  a.one_tile = 1u;
+  a.ordered = 0u;
+  a.pubcnt = ws ? ws->pubcnt : nullptr;
+  bool cooperative = false;
+  if (T > 1 && cf.mode == kModeOrdered) {
+    a.ordered = 1u;
+    a.total_acquires = 0;
+  } else if (T > 1 && cf.mode == kModeStatic) {
+    grid = std::min<int64_t>(T, resident_blocks(fn, threads, di.cus));
+    a.one_tile = 0u;
+    a.stride = (uint32_t)grid;
+    a.total_acquires = 0;
+    cooperative = true;
+  } else if (T > 1 && cf.mode == kModePersistent) {
+    grid = std::min<int64_t>(T, resident_blocks(fn, threads, di.cus));
+    a.one_tile = grid == T ? 1u : 0u;
+    a.total_acquires = a.one_tile ? (uint64_t)T : (uint64_t)(T + grid);
+  } else {
+    a.total_acquires = (uint64_t)T;
+  }
   if (c.seg && T > 1) {
     const int64_t cnt = T + 1;
     const int mb = 256;
@@ -275,7 +298,11 @@ scan_status_t launch(const Call &c, hipStream_t stream, Workspace *ws_override, 
     a.tile_seg = ws->map;
   }
   void *kargs[] = {&a};
-  hipError_t e = hipLaunchKernel(fn, dim3((unsigned)grid), dim3(sh.block), kargs, 0, stream);
+  // a cooperative launch guarantees that the whole grid is resident at once,
+  // which the static round robin needs for forward progress
+  hipError_t e = cooperative
+                     ? hipLaunchCooperativeKernel(fn, dim3((unsigned)grid), dim3(threads), kargs, 0, stream)
+                     : hipLaunchKernel(fn, dim3((unsigned)grid), dim3(threads), kargs, 0, stream);
   if (e != hipSuccess) return hip_fail(e);
   return SCAN_SUCCESS;
 }
@@ -612,13 +639,13 @@ scan_status_t scan_segmented_looped(const void *in, void *out, const int64_t *ho
 int32_t scan_num_configs(void) { return kNumConfigs; }
 
 scan_status_t scan_config_info(int32_t config, int32_t *block, int32_t *items, int32_t *nontemporal,
-                               int32_t *persistent) {
+                               int32_t *mode) {
   if (config < 0 || config >= kNumConfigs) return SCAN_ERROR_INVALID_VALUE;
   const KernelShape &sh = kShapes[kConfigs[config].shape];
   if (block) *block = sh.block;
   if (items) *items = sh.items;
   if (nontemporal) *nontemporal = sh.nontemporal;
-  if (persistent) *persistent = kConfigs[config].persistent;
+  if (mode) *mode = kConfigs[config].mode;
   return SCAN_SUCCESS;
 }
 
@@ -705,9 +732,9 @@ scan_status_t scan_tune_save(const char *path) {
         const KernelShape &sh = kShapes[kConfigs[cfg].shape];
         std::fprintf(f,
                      "%s\n    {\"op\": \"%s\", \"segmented\": %d, \"log2n\": %d, \"config\": %d, "
-                     "\"block\": %d, \"items\": %d, \"nontemporal\": %d, \"persistent\": %d}",
+                     "\"block\": %d, \"items\": %d, \"nontemporal\": %d, \"mode\": %d}",
                      first ? "" : ",", oc ? "f32" : "int", sg, b, cfg, sh.block, sh.items,
-                     sh.nontemporal, kConfigs[cfg].persistent);
+                     sh.nontemporal, kConfigs[cfg].mode);
         first = false;
       }
   std::fprintf(f, "\n  ]\n}\n");

@@ -163,30 +163,39 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 // ------------------------------------------------------------------ look-back
-// Run by one whole wave.  Lane l, slot k inspects predecessor t-1-(64k+l)
-// (distance d = 64k+l).  dP = nearest PREFIX, dE = nearest EMPTY.  The window
-// is usable when every word nearer than the PREFIX is an AGG; then the carry is
-// the PREFIX value folded left with the AGG values of distances dP-1 .. 0.
-// Integers may also consume a window of AGGs and continue further back
-// (addition is exact); float64 carries wait until the PREFIX is in the window
-// so that the fold order is always the canonical left-to-right chain.
-// Returns the exclusive carry into tile t (t >= 1).
+// Run by one whole wave.  Lane l, slot k inspects predecessor base-(64k+l)
+// (distance d = 64k+l from tile t = base+1).  dP = nearest PREFIX, dE =
+// nearest EMPTY.  The window is usable when every word nearer than the PREFIX
+// is an AGG; then the carry is the PREFIX value folded left with the AGG
+// values of distances dP-1 .. 0.  Integers may also consume a window of AGGs
+// and continue further back (addition is exact); float64 carries wait until
+// the PREFIX is in the window so that the fold order is always the canonical
+// left-to-right chain.
+
+// Issue the loads of one window (indices below 0 read as an empty PREFIX).
+template <class Op, int K>
+__device__ __forceinline__ void lb_window(const uint64_t *st, int64_t base, uint64_t (&w)[K]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t idx = base - (int64_t)(64 * k + lane);
+    w[k] = idx >= 0 ? ld_agent(st + idx) : Op::pack(Op::czero(), kPrefix);
+  }
+}
+
+// Exclusive carry into tile t (t >= 1), starting from an already issued
+// window w of base t-1.
 template <class Op, int K>
 __device__ typename Op::carry_t look_back(const uint64_t *st, int64_t t, uint32_t spin_limit,
-                                          WsHeader *hdr) {
+                                          WsHeader *hdr, uint64_t (&w)[K]) {
   using carry_t = typename Op::carry_t;
   const int lane = threadIdx.x & 63;
   carry_t acc = Op::czero();
   int64_t base = t - 1;
   uint32_t spins = 0;
   constexpr int kNone = 1 << 30;
-  for (;;) {
-    uint64_t w[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int64_t idx = base - (int64_t)(64 * k + lane);
-      w[k] = idx >= 0 ? ld_agent(st + idx) : Op::pack(Op::czero(), kPrefix);
-    }
+  for (bool fresh = true;; fresh = false) {
+    if (!fresh) lb_window<Op, K>(st, base, w);
     int dP = kNone, dE = kNone;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -227,64 +236,399 @@ __device__ typename Op::carry_t look_back(const uint64_t *st, int64_t t, uint32_
       part = Op::narrow(readlane32(Op::lbits(wave_scan<Op>(part)), 63));
       return Op::cadd(acc, part);
     } else {
-      auto slot = [&](int d) -> uint64_t {
-        const int k = d >> 6;
-        uint64_t sel = w[0];
+      // left fold from the PREFIX at distance dP down to distance 0; the
+      // window index k is kept static so no private array is indexed
+      // dynamically
+      carry_t c = Op::czero();
 #pragma unroll
-        for (int kk = 1; kk < K; ++kk) sel = (k == kk) ? w[kk] : sel;
-        return readlane64(sel, d & 63);
-      };
-      carry_t c = Op::value_of(slot(dP));
-      for (int d = dP - 1; d >= 0; --d) c = Op::canon(Op::cadd(c, Op::value_of(slot(d))));
+      for (int k = 0; k < K; ++k)
+        if (k == (dP >> 6)) c = Op::value_of(readlane64(w[k], dP & 63));
+#pragma unroll
+      for (int k = K - 1; k >= 0; --k) {
+        int l = dP - 1 - 64 * k;
+        if (l > 63) l = 63;
+        for (; l >= 0; --l) c = Op::canon(Op::cadd(c, Op::value_of(readlane64(w[k], l))));
+      }
       return c;
     }
   }
 }
 
-// Physical index of the lowest element of the 4-element group that lane
-// `lane` of wave `wave` holds in chunk c.  Logical element e of a tile is
-// physical pb+e going forward and pb+TILE-1-e in reverse, so a reverse tile is
-// the same aligned block read back to front.
-template <int TILE, int WSPAN>
-__device__ __forceinline__ int64_t quad_base(uint32_t reverse, int64_t pb, int wave, int c, int lane) {
-  const int e0 = wave * WSPAN + c * 256 + lane * 4;
-  return reverse ? (pb + TILE - 4 - e0) : (pb + e0);
+// Tile addressing.  Logical element e of a tile is physical pb+e going
+// forward and pb+TILE-1-e in reverse (a reverse tile is the same aligned block
+// read back to front).  Wave w owns logical [w*WSPAN, (w+1)*WSPAN); in chunk c
+// lane l holds the 4-group of logical c*256+4l .. c*256+4l+3.  The group's
+// lowest physical index is wave_base + quad_off: wave_base is uniform per
+// wave (scalar registers), quad_off is a small non-negative per-lane offset
+// minus a per-chunk constant, which the compiler folds into the load's
+// immediate offset.
+template <bool REV, int TILE, int WSPAN>
+__device__ __forceinline__ int64_t wave_base(int64_t pb, int wave) {
+  return REV ? pb + TILE - (int64_t)WSPAN * (wave + 1) : pb + (int64_t)WSPAN * wave;
+}
+template <bool REV, int WSPAN>
+__device__ __forceinline__ int quad_off(int c, int lane) {
+  return REV ? (WSPAN - 4 - lane * 4) - c * 256 : lane * 4 + c * 256;
+}
+__device__ __forceinline__ int wave_id() {
+  return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
 }
 
-// ------------------------------------------------------------------- kernel
-template <class Op, int BLOCK, int ITEMS, bool SEG, bool NT>
-__global__ void __launch_bounds__(BLOCK) scan_tiles(KernelArgs a) {
+// Hands the workspace to the next launch: clean the rest of the other status
+// array and flip the parity.  Called once per launch, by a workgroup that
+// knows every workgroup of the launch has already read the parity.
+__device__ __forceinline__ void hand_over(const KernelArgs &a, uint32_t p, uint64_t clear_hi, int tid,
+                                          int nthreads) {
+  uint64_t *other = a.status + (1 - p) * a.capacity;
+  for (uint64_t i = (uint64_t)a.tiles + tid; i < clear_hi; i += nthreads) st_agent(other + i, 0ull);
+  if (tid == 0) {
+    st_agent(&a.hdr->counter[1 - p], 0ull);
+    st_agent(&a.hdr->dirty[1 - p], 0ull);
+    st_agent(&a.hdr->dirty[p], (uint64_t)a.tiles);
+    st_agent32(&a.hdr->parity, 1u - p);
+  }
+}
+
+// Compile-time shape of a tile: BLOCK threads, ITEMS elements each; wave w
+// owns the logical span [w*WSPAN, (w+1)*WSPAN) as CH chunks of 256.
+template <int BLOCK, int ITEMS>
+struct Shape {
   static_assert(BLOCK % 64 == 0 && ITEMS % 4 == 0, "shape");
-  constexpr int WAVES = BLOCK / 64;
-  constexpr int CH = ITEMS / 4;            // 256-element chunks per wave
-  constexpr int WSPAN = 64 * ITEMS;        // contiguous elements per wave
-  constexpr int TILE = BLOCK * ITEMS;
-  constexpr int K = 2;                     // look-back window = 64*K tiles
+  static constexpr int WAVES = BLOCK / 64;
+  static constexpr int CH = ITEMS / 4;
+  static constexpr int WSPAN = 64 * ITEMS;
+  static constexpr int TILE = BLOCK * ITEMS;
+};
+
+// ---------------------------------------------------------------- tile steps
+// Segment starts of tile t as an LDS bitmap (TILE bits, logical order).  Whole
+// workgroup (contains barriers).  Returns whether any start was marked.
+template <int BLOCK, int TILE, bool REV>
+__device__ bool mark_heads(const KernelArgs &a, int64_t t, uint32_t *heads, uint32_t *flag) {
+  const int tid = threadIdx.x;
+  const int64_t ptile = REV ? (a.tiles - 1 - t) : t;
+  const int64_t pb = ptile * (int64_t)TILE;
+  const int64_t rem = a.n - pb;
+  const int valid = rem < TILE ? (int)rem : TILE;
+  int64_t s_lo, s_hi;
+  if (a.tile_seg) {
+    s_lo = a.tile_seg[ptile];
+    s_hi = a.tile_seg[ptile + 1];
+  } else {
+    s_lo = 0;
+    s_hi = a.num_segments + 1;
+  }
+  if (s_hi <= s_lo) return false;
+  for (int i = tid; i < TILE / 32; i += BLOCK) heads[i] = 0u;
+  if (tid == 0) *flag = 0u;
+  __syncthreads();
+  const int shift = REV ? 1 : 0;
+  for (int64_t s = s_lo + tid; s < s_hi; s += BLOCK) {
+    const bool real = REV ? (s >= 1) : (s < a.num_segments);
+    const int64_t ph = a.offsets[s] - shift;   // physical first element (last for reverse)
+    if (real && ph >= pb && ph < pb + valid) {
+      const int e = REV ? (TILE - 1 - (int)(ph - pb)) : (int)(ph - pb);
+      atomicOr(&heads[e >> 5], 1u << (e & 31));
+      *flag = 1u;
+    }
+  }
+  __syncthreads();
+  return *flag != 0u;
+}
+
+// Issue the loads of tile t into R; all are issued before any is used (the
+// branch is outside the chunk loop).  Partial tiles and misaligned inputs take
+// the element-wise path, identity-padded.
+template <class SH, bool NT, bool REV>
+__device__ __forceinline__ void load_tile(const KernelArgs &a, int64_t t, int wave, int lane,
+                                          u32x4 (&R)[SH::CH]) {
+  const int64_t ptile = REV ? (a.tiles - 1 - t) : t;
+  const int64_t pb = ptile * (int64_t)SH::TILE;
+  const int64_t wb = wave_base<REV, SH::TILE, SH::WSPAN>(pb, wave);
+  const uint32_t *wp = static_cast<const uint32_t *>(a.in) + wb;
+  if (pb + SH::TILE <= a.n && a.vec_in) {
+#pragma unroll
+    for (int c = 0; c < SH::CH; ++c) R[c] = load4<NT>(wp + quad_off<REV, SH::WSPAN>(c, lane));
+  } else {
+    // element j of chunk c is valid iff lb + j < lim - coff(c): the
+    // lane-dependent side takes 4 values, the other side is uniform
+    const int64_t remw = a.n - wb;
+    const int lim = remw <= 0 ? 0 : (remw >= SH::WSPAN ? SH::WSPAN : (int)remw);
+    const int lb = quad_off<REV, SH::WSPAN>(0, lane);
+#pragma unroll
+    for (int c = 0; c < SH::CH; ++c) {
+      const int coff = REV ? -c * 256 : c * 256;
+      const int room = lim - coff;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) R[c][j] = (lb + j < room) ? wp[lb + coff + j] : 0u;
+    }
+  }
+}
+
+template <class SH, bool NT, bool REV>
+__device__ __forceinline__ void store_tile(const KernelArgs &a, int64_t t, int wave, int lane,
+                                           u32x4 (&R)[SH::CH]) {
+  const int64_t ptile = REV ? (a.tiles - 1 - t) : t;
+  const int64_t pb = ptile * (int64_t)SH::TILE;
+  const int64_t wb = wave_base<REV, SH::TILE, SH::WSPAN>(pb, wave);
+  uint32_t *wp = static_cast<uint32_t *>(a.out) + wb;
+  if (pb + SH::TILE <= a.n && a.vec_out) {
+#pragma unroll
+    for (int c = 0; c < SH::CH; ++c) store4<NT>(wp + quad_off<REV, SH::WSPAN>(c, lane), R[c]);
+  } else {
+    const int64_t remw = a.n - wb;
+    const int lim = remw <= 0 ? 0 : (remw >= SH::WSPAN ? SH::WSPAN : (int)remw);
+    const int lb = quad_off<REV, SH::WSPAN>(0, lane);
+#pragma unroll
+    for (int c = 0; c < SH::CH; ++c) {
+      const int coff = REV ? -c * 256 : c * 256;
+      const int room = lim - coff;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (lb + j < room) wp[lb + coff + j] = R[c][j];
+    }
+  }
+}
+
+// In-register scan of this wave's span (the 64-lane form of the horizontal
+// in-register scan of Section 3.1, chained over the chunks).  On return
+// R[c][k] holds the wave-local value of logical element k of chunk c
+// (inclusive or exclusive, restarted at segment starts), am[c] (segmented)
+// marks the elements that the carry into the wave still applies to, and
+// (wsum, wflag) is the wave's total (since its last segment start) and
+// whether it contains a start.
+template <class Op, class SH, bool SEG, bool REV>
+__device__ __forceinline__ void scan_wave(uint32_t exclusive, int wave, int lane, bool any_head,
+                                          const uint32_t *heads, u32x4 (&R)[SH::CH],
+                                          uint32_t (&am)[SEG ? SH::CH : 1],
+                                          typename Op::carry_t &wsum_out, uint32_t &wflag_out) {
   using lane_t = typename Op::lane_t;
   using carry_t = typename Op::carry_t;
+  carry_t wsum = Op::czero();
+  uint32_t wflag = 0u;
+#pragma unroll
+  for (int c = 0; c < SH::CH; ++c) {
+    if (REV) {
+      const uint32_t x0 = R[c][0], x1 = R[c][1];
+      R[c][0] = R[c][3];
+      R[c][1] = R[c][2];
+      R[c][2] = x1;
+      R[c][3] = x0;
+    }
+    uint32_t hb = 0u;   // segment starts among this lane's 4 elements (bit k)
+    if constexpr (SEG) {
+      if (any_head) {
+        const int e0 = wave * SH::WSPAN + c * 256 + lane * 4;
+        hb = (heads[e0 >> 5] >> (e0 & 31)) & 0xfu;
+      }
+    }
+    // in-lane inclusive partials, restarting at segment starts
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+      const lane_t sum = Op::ladd(Op::lfrom(R[c][k - 1]), Op::lfrom(R[c][k]));
+      if constexpr (SEG) R[c][k] = ((hb >> k) & 1u) ? R[c][k] : Op::lbits(sum);
+      else R[c][k] = Op::lbits(sum);
+    }
+    lane_t x = Op::lfrom(R[c][3]);
+    uint32_t f = hb != 0u;
+    uint32_t cf = 0u;
+    if constexpr (SEG) {
+      wave_scan_seg<Op>(x, f);
+      cf = readlane32(f, 63);
+    } else {
+      x = wave_scan<Op>(x);
+    }
+    const lane_t lex = Op::lfrom(lane_up1(Op::lbits(x)));   // lane-exclusive value in the chunk
+    const lane_t ct = Op::lfrom(readlane32(Op::lbits(x), 63));
+    // chunk-local values; m marks the elements the carry into the chunk applies to
+    uint32_t m = 0xfu;
+    if constexpr (SEG) {
+      const uint32_t lexf = lane_up1(f);   // a segment starts in an earlier lane of the chunk
+      m = 0u;
+      if (exclusive) {
+        // out_k = head_k ? 0 : value before k in its segment
+#pragma unroll
+        for (int k = 3; k >= 0; --k) {
+          const uint32_t h = (hb >> k) & 1u;
+          const uint32_t before = hb & ((1u << k) - 1u);   // starts strictly before k in the lane
+          const lane_t prev = k ? Op::lfrom(R[c][k - 1]) : Op::lzero();
+          const lane_t v = h ? Op::lzero() : (before ? prev : (k ? Op::ladd(lex, prev) : lex));
+          R[c][k] = Op::lbits(v);
+          m |= (!h && !before && !lexf) ? (1u << k) : 0u;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t seen = hb & ((2u << k) - 1u);      // starts at or before k
+          if (!seen) R[c][k] = Op::lbits(Op::ladd(lex, Op::lfrom(R[c][k])));
+          m |= (!seen && !lexf) ? (1u << k) : 0u;
+        }
+      }
+    } else {
+      if (exclusive) {
+        R[c][3] = Op::lbits(Op::ladd(lex, Op::lfrom(R[c][2])));
+        R[c][2] = Op::lbits(Op::ladd(lex, Op::lfrom(R[c][1])));
+        R[c][1] = Op::lbits(Op::ladd(lex, Op::lfrom(R[c][0])));
+        R[c][0] = Op::lbits(lex);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) R[c][k] = Op::lbits(Op::ladd(lex, Op::lfrom(R[c][k])));
+      }
+    }
+    // fold the chunk's prefix within the wave (uniform) into its elements
+    if (c > 0) {
+      const lane_t cp = Op::narrow(wsum);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if ((m >> k) & 1u) R[c][k] = Op::lbits(Op::ladd(cp, Op::lfrom(R[c][k])));
+      if (wflag) m = 0u;   // a segment started in an earlier chunk of this wave
+    }
+    if constexpr (SEG) am[c] = m;
+    wsum = cf ? Op::widen(ct) : Op::cadd(wsum, Op::widen(ct));
+    wflag |= cf;
+  }
+  wsum_out = wsum;
+  wflag_out = wflag;
+}
 
-  __shared__ carry_t s_wtot[WAVES];
-  __shared__ uint32_t s_wflag[WAVES];
+// Wave totals through LDS: this wave's exclusive prefix (wpre, wpref) and
+// the tile aggregate (agg, aggf), all folded left to right.  Contains one
+// barrier.
+template <class Op, int WAVES>
+__device__ __forceinline__ void combine_waves(int wave, int lane, typename Op::carry_t wsum, uint32_t wflag,
+                                              typename Op::carry_t *s_wtot, uint32_t *s_wflag,
+                                              typename Op::carry_t &wpre, uint32_t &wpref,
+                                              typename Op::carry_t &agg, uint32_t &aggf) {
+  if (lane == 0) {
+    s_wtot[wave] = wsum;
+    s_wflag[wave] = wflag;
+  }
+  __syncthreads();
+  wpre = Op::czero();
+  agg = Op::czero();
+  wpref = 0u;
+  aggf = 0u;
+#pragma unroll
+  for (int w = 0; w < WAVES; ++w) {
+    if (w == wave) {
+      wpre = agg;
+      wpref = aggf;
+    }
+    const typename Op::carry_t tw = s_wtot[w];
+    const uint32_t fw = s_wflag[w];
+    agg = fw ? tw : Op::cadd(agg, tw);
+    aggf |= fw;
+  }
+}
+
+// Wave 0: the tile's first status word.  Tile 0 and tiles that contain a
+// segment start know their inclusive prefix at once; the others publish
+// their aggregate.
+template <class Op>
+__device__ __forceinline__ void publish_first(uint64_t *st, int64_t t, typename Op::carry_t agg, uint32_t aggf) {
+  if ((threadIdx.x & 63) != 0) return;
+  if (t == 0 || aggf) {
+    const typename Op::carry_t pv =
+        (t == 0 && !aggf) ? Op::canon(Op::cadd(Op::czero(), Op::canon(agg))) : Op::canon(agg);
+    st_agent(st + t, Op::pack(pv, kPrefix));
+  } else {
+    st_agent(st + t, Op::pack(agg, kAgg));
+  }
+}
+
+// Add the carry into each wave and store.  out = win + R where the carry
+// applies (every element unless segmented).
+template <class Op, class SH, bool SEG, bool NT, bool REV>
+__device__ __forceinline__ void finish_tile(const KernelArgs &a, int64_t t, int wave, int lane,
+                                            typename Op::carry_t win, u32x4 (&R)[SH::CH],
+                                            const uint32_t (&am)[SEG ? SH::CH : 1]) {
+  using lane_t = typename Op::lane_t;
+  const lane_t w32 = Op::narrow(win);
+#pragma unroll
+  for (int c = 0; c < SH::CH; ++c) {
+    lane_t o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const lane_t l = Op::lfrom(R[c][k]);
+      if constexpr (SEG) o[k] = ((am[c] >> k) & 1u) ? Op::ladd(w32, l) : l;
+      else o[k] = Op::ladd(w32, l);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) R[c][k] = Op::lbits(REV ? o[3 - k] : o[k]);
+  }
+  store_tile<SH, NT, REV>(a, t, wave, lane, R);
+}
+
+// End of a workgroup in a static round-robin launch: count it; the last
+// workgroup (all others have finished, so all have read the parity) hands
+// the workspace over.  The counter of the launch's parity serves as the
+// count; the hand-over clears the other parity's counter for the next launch.
+__device__ __forceinline__ void static_done(const KernelArgs &a, uint32_t parity, int tid, int nthreads,
+                                            uint32_t *flag, uint64_t *clear_hi) {
+  __syncthreads();
+  if (tid == 0) {
+    const uint64_t d = __hip_atomic_fetch_add(&a.hdr->counter[parity], 1ull, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    *flag = d == (uint64_t)gridDim.x - 1;
+    if (*flag) *clear_hi = ld_agent(&a.hdr->dirty[1 - parity]);
+  }
+  __syncthreads();
+  if (*flag) hand_over(a, parity, *clear_hi, tid, nthreads);
+}
+
+// ------------------------------------------------------------------- kernels
+// One tile per workgroup iteration.  Tile numbers come either from the device
+// counter (dynamic: any workgroup that waits depends only on workgroups that
+// are already running) or, with `ordered`, from blockIdx.x (no counter; this
+// relies on the dispatcher starting workgroups in index order, so a
+// workgroup's predecessors have all been started before it).
+template <class Op, int BLOCK, int ITEMS, bool SEG, bool NT, bool REV>
+__global__ void __launch_bounds__(BLOCK) scan_tiles(KernelArgs a) {
+  using SH = Shape<BLOCK, ITEMS>;
+  constexpr int K = 4;   // look-back window = 64*K tiles per poll
+  using carry_t = typename Op::carry_t;
+
+  __shared__ carry_t s_wtot[SH::WAVES];
+  __shared__ uint32_t s_wflag[SH::WAVES];
   __shared__ carry_t s_carry;
   __shared__ uint64_t s_tile;
   __shared__ uint64_t s_clear_hi;
-  __shared__ uint32_t s_parity, s_last, s_has_heads;
-  __shared__ uint32_t s_heads[SEG ? TILE / 32 : 1];
+  __shared__ uint32_t s_parity, s_last, s_flag;
+  __shared__ uint32_t s_heads[SEG ? SH::TILE / 32 : 1];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = wave_id();
   const bool multi = a.tiles > 1;
-  const uint32_t *in = static_cast<const uint32_t *>(a.in);
-  uint32_t *out = static_cast<uint32_t *>(a.out);
   uint32_t parity = 0;
 
   for (int iter = 0;; ++iter) {
-    // ------------------------------------------------ 1. acquire a tile
+    // ------------------------------------------------ acquire a tile
     int64_t t;
     if (!multi) {
       if (iter > 0) break;
       t = 0;
+    } else if (a.ordered) {
+      if (iter > 0) break;
+      t = blockIdx.x;
+      if (tid == 0) {
+        parity = ld_agent32(&a.hdr->parity);
+        st_agent(a.status + (1 - parity) * a.capacity + t, 0ull);
+        s_parity = parity;
+        s_clear_hi = (t == a.tiles - 1) ? ld_agent(&a.hdr->dirty[1 - parity]) : 0ull;
+      }
+      __syncthreads();
+      parity = s_parity;
+    } else if (a.stride) {
+      // static round robin over a co-resident grid
+      t = (int64_t)blockIdx.x + (int64_t)iter * a.stride;
+      if (iter == 0) {
+        if (tid == 0) s_parity = ld_agent32(&a.hdr->parity);
+        __syncthreads();
+        parity = s_parity;
+      }
+      if (t >= a.tiles) break;
+      if (tid == 0) st_agent(a.status + (1 - parity) * a.capacity + t, 0ull);
     } else {
       if (tid == 0) {
         if (iter == 0) parity = ld_agent32(&a.hdr->parity);
@@ -300,167 +644,39 @@ __global__ void __launch_bounds__(BLOCK) scan_tiles(KernelArgs a) {
       __syncthreads();
       t = (int64_t)s_tile;
       const uint32_t p = s_parity;
-      if (s_last) {
-        // last increment of this launch: finish cleaning the other array and
-        // hand the workspace to the next launch
-        uint64_t *other = a.status + (1 - p) * a.capacity;
-        for (uint64_t i = (uint64_t)a.tiles + tid; i < s_clear_hi; i += BLOCK) st_agent(other + i, 0ull);
-        if (tid == 0) {
-          st_agent(&a.hdr->counter[1 - p], 0ull);
-          st_agent(&a.hdr->dirty[1 - p], 0ull);
-          st_agent(&a.hdr->dirty[p], (uint64_t)a.tiles);
-          st_agent32(&a.hdr->parity, 1u - p);
-        }
-      }
+      // last increment of this launch: every workgroup has read the parity
+      if (s_last) hand_over(a, p, s_clear_hi, tid, BLOCK);
       if (t >= a.tiles) break;
       parity = p;
     }
 
-    const int64_t ptile = a.reverse ? (a.tiles - 1 - t) : t;   // physical tile
-    const int64_t pb = ptile * (int64_t)TILE;
-    const int64_t rem = a.n - pb;
-    const int valid = rem < TILE ? (int)rem : TILE;
-    const bool full = valid == TILE;
-
-    // ------------------------------------------------ segment starts (LDS bitmap)
     bool any_head = false;
-    if constexpr (SEG) {
-      int64_t s_lo, s_hi;
-      if (a.tile_seg) {
-        s_lo = a.tile_seg[ptile];
-        s_hi = a.tile_seg[ptile + 1];
-      } else {
-        s_lo = 0;
-        s_hi = a.num_segments + 1;
-      }
-      if (s_hi > s_lo) {
-        for (int i = tid; i < TILE / 32; i += BLOCK) s_heads[i] = 0u;
-        if (tid == 0) s_has_heads = 0u;
-        __syncthreads();
-        const int shift = a.reverse ? 1 : 0;
-        for (int64_t s = s_lo + tid; s < s_hi; s += BLOCK) {
-          const bool real = a.reverse ? (s >= 1) : (s < a.num_segments);
-          const int64_t ph = a.offsets[s] - shift;   // physical first element (last for reverse)
-          if (real && ph >= pb && ph < pb + valid) {
-            const int e = a.reverse ? (TILE - 1 - (int)(ph - pb)) : (int)(ph - pb);
-            atomicOr(&s_heads[e >> 5], 1u << (e & 31));
-            s_has_heads = 1u;
-          }
-        }
-        __syncthreads();
-        any_head = s_has_heads != 0u;
-      }
-    }
+    if constexpr (SEG) any_head = mark_heads<BLOCK, SH::TILE, REV>(a, t, s_heads, &s_flag);
 
-    // ------------------------------------------------ 2. load the tile once
-    // raw[c] holds 4 consecutive physical elements; all loads of the tile are
-    // issued before any is consumed (the branch is outside the chunk loop so
-    // the compiler waits once, not once per chunk).
-    u32x4 raw[CH];
-    if (full && a.vec_in) {
-#pragma unroll
-      for (int c = 0; c < CH; ++c) raw[c] = load4<NT>(in + quad_base<TILE, WSPAN>(a.reverse, pb, wave, c, lane));
-    } else {
-#pragma unroll
-      for (int c = 0; c < CH; ++c) {
-        const int64_t q = quad_base<TILE, WSPAN>(a.reverse, pb, wave, c, lane);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) raw[c][j] = (q + j < a.n) ? in[q + j] : 0u;
-      }
-    }
-    lane_t v[CH][4];
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) v[c][k] = Op::lfrom(a.reverse ? raw[c][3 - k] : raw[c][k]);
-    }
+    // load once, scan in registers, combine the waves
+    u32x4 R[SH::CH];
+    uint32_t am[SEG ? SH::CH : 1];
+    load_tile<SH, NT, REV>(a, t, wave, lane, R);
+    carry_t wsum, wpre, agg;
+    uint32_t wflag, wpref, aggf;
+    scan_wave<Op, SH, SEG, REV>(a.exclusive, wave, lane, any_head, s_heads, R, am, wsum, wflag);
+    combine_waves<Op, SH::WAVES>(wave, lane, wsum, wflag, s_wtot, s_wflag, wpre, wpref, agg, aggf);
 
-    // ------------------------------------------------ 3. lane and wave scans
-    uint32_t hb[CH];          // segment starts among this lane's 4 elements (bit k)
-    lane_t lex[CH];           // lane-exclusive value within the chunk
-    uint32_t lexf[CH];        // a segment starts in an earlier lane of the chunk
-    lane_t ctot[CH];          // chunk total (lane 63 of the scan)
-    uint32_t cflag[CH];
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      hb[c] = 0u;
-      if constexpr (SEG) {
-        if (any_head) {
-          const int e0 = wave * WSPAN + c * 256 + lane * 4;
-          hb[c] = (s_heads[e0 >> 5] >> (e0 & 31)) & 0xfu;
-        }
-      }
-      // in-lane inclusive partials, restarting at segment starts
-#pragma unroll
-      for (int k = 1; k < 4; ++k) {
-        if constexpr (SEG) v[c][k] = ((hb[c] >> k) & 1u) ? v[c][k] : Op::ladd(v[c][k - 1], v[c][k]);
-        else v[c][k] = Op::ladd(v[c][k - 1], v[c][k]);
-      }
-      lane_t x = v[c][3];
-      uint32_t f = hb[c] != 0u;
-      if constexpr (SEG) {
-        wave_scan_seg<Op>(x, f);
-        lexf[c] = lane_up1(f);
-        cflag[c] = readlane32(f, 63);
-      } else {
-        x = wave_scan<Op>(x);
-        lexf[c] = 0u;
-        cflag[c] = 0u;
-      }
-      lex[c] = Op::lfrom(lane_up1(Op::lbits(x)));
-      ctot[c] = Op::lfrom(readlane32(Op::lbits(x), 63));
-    }
-
-    // chunk chain within the wave (uniform values)
-    carry_t cpre[CH];
-    uint32_t cpref[CH];
-    carry_t wsum = Op::czero();
-    uint32_t wflag = 0u;
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      cpre[c] = wsum;
-      cpref[c] = wflag;
-      wsum = cflag[c] ? Op::widen(ctot[c]) : Op::cadd(wsum, Op::widen(ctot[c]));
-      wflag |= cflag[c];
-    }
-
-    // ------------------------------------------------ 4. block combine
-    if (lane == 0) {
-      s_wtot[wave] = wsum;
-      s_wflag[wave] = wflag;
-    }
-    __syncthreads();
-    carry_t wpre = Op::czero(), agg = Op::czero();
-    uint32_t wpref = 0u, aggf = 0u;
-#pragma unroll
-    for (int w = 0; w < WAVES; ++w) {
-      if (w == wave) {
-        wpre = agg;
-        wpref = aggf;
-      }
-      const carry_t tw = s_wtot[w];
-      const uint32_t fw = s_wflag[w];
-      agg = fw ? tw : Op::cadd(agg, tw);
-      aggf |= fw;
-    }
-
-    // ------------------------------------------------ 5. publish and look back
+    // publish, look back, publish the prefix
     bool first_is_head = false;
     if constexpr (SEG) first_is_head = any_head && (s_heads[0] & 1u);
     const bool need_carry = t > 0 && !first_is_head;
     if (multi && wave == 0) {
       uint64_t *st = a.status + parity * a.capacity;
-      if (t == 0 || aggf) {
-        // tile 0 and tiles containing a segment start know their prefix now
-        const carry_t pv = (t == 0 && !aggf) ? Op::canon(Op::cadd(Op::czero(), Op::canon(agg)))
-                                             : Op::canon(agg);
-        if (lane == 0) st_agent(st + t, Op::pack(pv, kPrefix));
-      } else if (lane == 0) {
-        st_agent(st + t, Op::pack(agg, kAgg));
-      }
+      publish_first<Op>(st, t, agg, aggf);
+      if (a.ordered && lane == 0 && t != a.tiles - 1)
+        (void)__hip_atomic_fetch_add(a.pubcnt + (parity * kPubSlots + (t % kPubSlots)) * kPubStride, 1ull,
+                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       carry_t carry = Op::czero();
       if (need_carry) {
-        carry = look_back<Op, K>(st, t, a.spin_limit, a.hdr);
+        uint64_t w[K];
+        lb_window<Op, K>(st, t - 1, w);
+        carry = look_back<Op, K>(st, t, a.spin_limit, a.hdr, w);
         if (!aggf && lane == 0)
           st_agent(st + t, Op::pack(Op::canon(Op::cadd(carry, Op::canon(agg))), kPrefix));
       }
@@ -469,56 +685,37 @@ __global__ void __launch_bounds__(BLOCK) scan_tiles(KernelArgs a) {
     __syncthreads();
     const carry_t carry = need_carry ? s_carry : Op::czero();
 
-    // ------------------------------------------------ 6. add the carry and store once
-    const carry_t win = wpref ? wpre : Op::cadd(carry, wpre);   // carry into this wave
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      const carry_t cin = cpref[c] ? cpre[c] : Op::cadd(win, cpre[c]);
-      const lane_t L = Op::narrow(lexf[c] ? Op::widen(lex[c]) : Op::cadd(cin, Op::widen(lex[c])));
-      lane_t o[4];
-      if constexpr (SEG) {
-        uint32_t seen = 0u;   // a segment starts at or before element k in this lane
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const uint32_t h = (hb[c] >> k) & 1u;
-          if (a.exclusive) {
-            o[k] = h ? Op::lzero() : (seen ? v[c][k - (k > 0)] : (k == 0 ? L : Op::ladd(L, v[c][k - (k > 0)])));
-          } else {
-            seen |= h;
-            o[k] = seen ? v[c][k] : Op::ladd(L, v[c][k]);
-          }
-          if (a.exclusive) seen |= h;
-        }
-      } else {
-        if (a.exclusive) {
-          o[0] = L;
-          o[1] = Op::ladd(L, v[c][0]);
-          o[2] = Op::ladd(L, v[c][1]);
-          o[3] = Op::ladd(L, v[c][2]);
-        } else {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) o[k] = Op::ladd(L, v[c][k]);
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) raw[c][k] = Op::lbits(a.reverse ? o[3 - k] : o[k]);
-    }
-    if (full && a.vec_out) {
-#pragma unroll
-      for (int c = 0; c < CH; ++c) store4<NT>(out + quad_base<TILE, WSPAN>(a.reverse, pb, wave, c, lane), raw[c]);
-    } else {
-#pragma unroll
-      for (int c = 0; c < CH; ++c) {
-        const int64_t q = quad_base<TILE, WSPAN>(a.reverse, pb, wave, c, lane);
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (q + j < a.n) out[q + j] = raw[c][j];
-      }
-    }
+    // add the carry and store once
+    finish_tile<Op, SH, SEG, NT, REV>(a, t, wave, lane, wpref ? wpre : Op::cadd(carry, wpre), R, am);
 
+    if (multi && a.ordered) {
+      if (t == a.tiles - 1) {
+        // wait until every other tile has published (so every workgroup of
+        // the launch has read the parity), then hand the workspace over
+        if (wave == 0) {
+          const uint64_t *cnt = a.pubcnt + (parity * kPubSlots + lane) * kPubStride;
+          for (uint32_t spins = 0;; ++spins) {
+            uint32_t c = (uint32_t)ld_agent(cnt);
+            c = readlane32(wave_scan<OpsU32>(c), 63);
+            if ((int64_t)c >= a.tiles - 1) break;
+            if (spins > a.spin_limit) {
+              if (lane == 0) st_agent32(&a.hdr->error, 1u);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
+          // the next launch uses the other parity's counters
+          st_agent(a.pubcnt + ((1 - parity) * kPubSlots + lane) * kPubStride, 0ull);
+        }
+        __syncthreads();
+        hand_over(a, parity, s_clear_hi, tid, BLOCK);
+      }
+      break;
+    }
     if (a.one_tile || !multi) break;
     __syncthreads();   // LDS is reused by the next tile
   }
+  if (multi && a.stride) static_done(a, parity, tid, BLOCK, &s_flag, &s_clear_hi);
 }
 
 // For each tile boundary p in [0, T]: the first segment index s with

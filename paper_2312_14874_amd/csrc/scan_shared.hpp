@@ -46,6 +46,16 @@ struct KernelArgs {
   uint32_t vec_in;            // in is 16-byte aligned
   uint32_t vec_out;           // out is 16-byte aligned
   uint32_t one_tile;          // every workgroup takes exactly one tile
+  uint32_t ordered;           // tile = blockIdx.x (no counter; relies on in-order dispatch)
+  uint32_t stride;            // static round robin: workgroup b takes tiles b, b+stride, ... (co-resident grid)
+  uint64_t *pubcnt;           // ordered mode: publish counters [2][kPubSlots], kPubStride words apart
 };
+
+// Ordered launches count published tiles in kPubSlots counters per parity
+// (spread over separate cache lines so their atomics do not serialise on one
+// address); the last tile waits for the count before handing over.
+constexpr int kPubSlots = 64;
+constexpr int kPubStride = 16;   // 128 bytes
+constexpr int kPubWords = 2 * kPubSlots * kPubStride;
 
 }  // namespace mi355scan

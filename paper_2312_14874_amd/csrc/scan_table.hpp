@@ -6,14 +6,21 @@ namespace mi355scan {
 
 struct KernelShape {
   int block;         // threads per workgroup
-  int items;         // elements per thread (multiple of 4)
+  int items;         // elements per thread (multiple of 4); the tile is block * items
   int nontemporal;   // non-temporal load/store hints
-  const void *fn[2][2];   // [0 = 32-bit integer, 1 = float32][segmented]
+  const void *fn[2][2][2];   // [0 = 32-bit integer, 1 = float32][segmented][reverse]
+};
+
+enum TileMode {
+  kModeCounter = 0,      // one tile per workgroup, tile numbers from the counter
+  kModePersistent = 1,   // resident grid looping over tiles from the counter
+  kModeOrdered = 2,      // tile number = workgroup index
+  kModeStatic = 4,       // resident grid (cooperative launch), static round robin
 };
 
 struct Config {
   int shape;         // index into kShapes
-  int persistent;    // grid = resident workgroups, tiles taken in a loop
+  int mode;          // TileMode
 };
 
 extern const KernelShape kShapes[];

@@ -204,7 +204,7 @@ def config_info(cfg: int) -> dict:
     b, i, nt, p = (ctypes.c_int32() for _ in range(4))
     check(lib.scan_config_info(cfg, ctypes.byref(b), ctypes.byref(i), ctypes.byref(nt), ctypes.byref(p)))
     return {"config": cfg, "block": b.value, "items": i.value, "nontemporal": nt.value,
-            "persistent": p.value, "tile": b.value * i.value}
+            "mode": p.value, "tile": b.value * i.value}
 
 
 def force_config(cfg: int = -1) -> None:

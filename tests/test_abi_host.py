@@ -92,7 +92,7 @@ def test_configs_are_well_formed():
     for c in range(n):
         info = config_info(c)
         assert info["block"] % 64 == 0 and info["items"] % 4 == 0
-        assert 2048 <= info["tile"] <= 32768
+        assert 2048 <= info["tile"] <= 65536 and info["mode"] in (0, 1, 2, 3, 4, 5)
 
 
 def test_tune_file_roundtrip(tmp_path):

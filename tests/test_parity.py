@@ -13,12 +13,18 @@ from gpu_util import assert_f32_close, configs, first_mismatch, flat
 
 pytestmark = pytest.mark.gpu
 
+try:
+    from paper_2312_14874_amd import num_configs
+    NUM_CONFIGS = num_configs()
+except ImportError:   # library not built: the GPU tests cannot run anyway
+    NUM_CONFIGS = 1
+
 
 def _sizes(tile):
     return [1, 63, 64, 65, 255, 257, tile - 1, tile, tile + 1, 3 * tile + 123, 131 * tile + 4099]
 
 
-@pytest.mark.parametrize("cfg", range(20))
+@pytest.mark.parametrize("cfg", range(NUM_CONFIGS))
 def test_u32_every_config(cfg):
     info = configs()[cfg]
     for n in _sizes(info["tile"]):
@@ -31,7 +37,7 @@ def test_u32_every_config(cfg):
                 assert not msg, "cfg %d n %d ex %d rev %d: %s" % (cfg, n, ex, rev, msg)
 
 
-@pytest.mark.parametrize("cfg", range(20))
+@pytest.mark.parametrize("cfg", range(NUM_CONFIGS))
 def test_f32_every_config(cfg):
     info = configs()[cfg]
     for n in (1, 257, info["tile"] + 1, 37 * info["tile"] + 999):
@@ -46,7 +52,7 @@ def test_f32_every_config(cfg):
                     assert got[first] == 0.0
 
 
-@pytest.mark.parametrize("cfg", [0, 2, 4, 12])
+@pytest.mark.parametrize("cfg", [0, 4, 6, 9])
 def test_f32_exact_when_sums_representable(cfg):
     # integers in [-2, 2], n <= 2^22: every partial sum fits in 24 bits
     for n in (5000, 1 << 20, (1 << 22) - 3):

@@ -9,8 +9,14 @@ from gpu_util import assert_f32_close, configs, first_mismatch, segmented
 
 pytestmark = pytest.mark.gpu
 
+try:
+    from paper_2312_14874_amd import num_configs
+    NUM_CONFIGS = num_configs()
+except ImportError:   # library not built: the GPU tests cannot run anyway
+    NUM_CONFIGS = 1
 
-@pytest.mark.parametrize("cfg", range(20))
+
+@pytest.mark.parametrize("cfg", range(NUM_CONFIGS))
 def test_int_random_offsets_every_config(cfg):
     g = np.random.default_rng(100 + cfg)
     tile = configs()[cfg]["tile"]
@@ -25,7 +31,7 @@ def test_int_random_offsets_every_config(cfg):
                 assert not msg, "cfg %d n %d S %d ex %d rev %d: %s" % (cfg, n, S, ex, rev, msg)
 
 
-@pytest.mark.parametrize("cfg", [2, 12, 0, 14])
+@pytest.mark.parametrize("cfg", [0, 2, 6, 9])
 def test_f32_segments(cfg):
     g = np.random.default_rng(cfg)
     tile = configs()[cfg]["tile"]
