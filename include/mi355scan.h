@@ -148,13 +148,23 @@ scan_status_t scan_segmented_looped(const void *in, void *out, const int64_t *ho
  * how tiles are assigned to workgroups.  A tuning table maps (dtype, flags, segmented, log2 n bucket)
  * to a configuration; built-in defaults can be replaced from a JSON file. */
 int32_t       scan_num_configs(void);
-/* mode: 0 = one tile per workgroup, tile numbers from a device counter;
- *       1 = persistent grid taking tiles from the counter;
+/* Describes configuration `config` (any output pointer may be NULL):
+ *  block, items: threads per workgroup and elements per thread (tile =
+ *    block * items elements);
+ *  nontemporal: 1 if tile loads and stores carry the non-temporal hint;
+ *  mode: how tiles reach workgroups:
+ *       0 = one tile per workgroup, tile numbers from a device counter;
+ *       1 = resident grid taking tiles from the counter;
  *       2 = tile number = workgroup index (no counter; relies on workgroups
  *           being dispatched in index order, bounded by the spin limit);
- *       4 = static round robin over a cooperatively launched resident grid. */
+ *       4 = static round robin over a cooperatively launched resident grid;
+ *  per_cu: resident-grid modes: workgroups per CU (0 = as many as fit);
+ *  cu_pct: resident-grid modes: percent of the CUs the grid covers.
+ * Inputs or outputs that are not 16-byte aligned always run a dword-access
+ * kernel (256 x 32, mode 1) whatever the configuration. */
 scan_status_t scan_config_info(int32_t config, int32_t *block, int32_t *items,
-                               int32_t *nontemporal, int32_t *mode);
+                               int32_t *nontemporal, int32_t *mode, int32_t *per_cu,
+                               int32_t *cu_pct);
 /* Force a configuration for subsequent calls (-1 = use the tuning table). */
 scan_status_t scan_force_config(int32_t config);
 /* Configuration the table selects for a call of this shape. */

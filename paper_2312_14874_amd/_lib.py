@@ -50,8 +50,8 @@ SIGNATURES = {
     "scan_graph_destroy": (ST, [P]),
     "scan_segmented_looped": (ST, [P, P, P, I32, ST, U32, P]),
     "scan_num_configs": (I32, []),
-    "scan_config_info": (ST, [I32, ctypes.POINTER(I32), ctypes.POINTER(I32),
-                              ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+    "scan_config_info": (ST, [I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32),
+                              ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]),
     "scan_force_config": (ST, [I32]),
     "scan_selected_config": (I32, [ST, U32, I32, I64]),
     "scan_autotune": (ST, [P, P, I64, P, I32, ST, U32, I32, P, ctypes.POINTER(I32)]),

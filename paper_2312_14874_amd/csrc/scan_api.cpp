@@ -27,8 +27,8 @@ namespace {
 // A legitimate wait never outlasts the whole kernel (about a millisecond at
 // 2^30 elements); 2^16 sleeping polls is of the order of 0.1 s.
 constexpr uint32_t kDefaultSpinLimit = 1u << 16;
-constexpr int kDefaultFlatConfig = 6;               // 256 threads x 128 items, resident grid
-constexpr int kDefaultSegConfig = 2;                // 256 threads x 64 items, tile = workgroup index
+constexpr int kDefaultFlatConfig = 22;  // 768 threads x 128 items, one resident workgroup per CU
+constexpr int kDefaultSegConfig = 4;    // 256 threads x 128 items, tile = workgroup index
 constexpr int kBuckets = 64;
 
 thread_local int t_last_hip = 0;
@@ -125,7 +125,7 @@ void ws_free(Workspace *w) {
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 
 int64_t min_tile() {
-  int64_t m = INT64_MAX;
+  int64_t m = (int64_t)kUnalignedShape.block * kUnalignedShape.items;
   for (int i = 0; i < kNumShapes; ++i) m = std::min<int64_t>(m, (int64_t)kShapes[i].block * kShapes[i].items);
   return m;
 }
@@ -196,6 +196,14 @@ int resident_blocks(const void *fn, int block, int cus) {
   return per_cu * cus;
 }
 
+// Workgroups of a resident grid: per_cu per CU when given (never more than
+// fit), else as many as fit, on cu_pct percent of the CUs.
+int64_t resident_grid(const void *fn, int block, int cus, int per_cu, int cu_pct) {
+  const int64_t fit = resident_blocks(fn, block, cus);
+  const int64_t want = per_cu > 0 ? std::min<int64_t>(fit, (int64_t)per_cu * cus) : fit;
+  return std::max<int64_t>(1, want * cu_pct / 100);
+}
+
 // ---------------------------------------------------------------- launching
 struct Call {
   const void *in;
@@ -208,11 +216,28 @@ struct Call {
   int64_t num_segments;
 };
 
+bool call_aligned(const Call &c) {
+  return ((uintptr_t)c.in & 15u) == 0 && ((uintptr_t)c.out & 15u) == 0;
+}
+
+// Kernel shape and tile mode a call runs with under configuration cfg:
+// buffers that are not 16-byte aligned take the dword-access kernels with a
+// resident grid.
+const KernelShape &call_shape(const Call &c, int cfg) {
+  return call_aligned(c) ? kShapes[kConfigs[cfg].shape] : kUnalignedShape;
+}
+int call_mode(const Call &c, int cfg) { return call_aligned(c) ? kConfigs[cfg].mode : (int)kModePersistent; }
+int call_per_cu(const Call &c, int cfg) { return call_aligned(c) ? kConfigs[cfg].per_cu : 0; }
+int call_cu_pct(const Call &c, int cfg) { return call_aligned(c) ? kConfigs[cfg].cu_pct : 100; }
+
 // Tiles a call of this shape needs under configuration cfg.
 int64_t call_tiles(const Call &c, int cfg) {
-  const KernelShape &sh = kShapes[kConfigs[cfg].shape];
+  const KernelShape &sh = call_shape(c, cfg);
   return tiles_for(c.n, (int64_t)sh.block * sh.items);
 }
+
+// Tile indices (and byte offsets into a status array) must fit in 32 bits.
+constexpr int64_t kMaxTiles = int64_t(1) << 29;
 
 // Enqueue one scan (plus the tile map for segmented calls).  ws_override is a
 // graph-owned workspace (already large enough) or null for the stream's own.
@@ -223,11 +248,14 @@ scan_status_t launch(const Call &c, hipStream_t stream, Workspace *ws_override, 
   scan_status_t s = current_device(&dev, &di);
   if (s != SCAN_SUCCESS) return s;
   const int cfg = cfg_override >= 0 ? cfg_override : select_config(c.opclass, c.seg, c.n);
-  const Config &cf = kConfigs[cfg];
-  const KernelShape &sh = kShapes[cf.shape];
+  const KernelShape &sh = call_shape(c, cfg);
+  const int mode = call_mode(c, cfg);
   const int64_t tile = (int64_t)sh.block * sh.items;
   const int64_t T = tiles_for(c.n, tile);
+  if (T > kMaxTiles) return SCAN_ERROR_NOT_SUPPORTED;
+  const int per_cu = call_per_cu(c, cfg);
   const void *fn = sh.fn[c.opclass][c.seg ? 1 : 0][(c.flags & SCAN_REVERSE) ? 1 : 0];
+  const int cu_pct = call_cu_pct(c, cfg);
 
   Workspace *ws = nullptr;
   if (T > 1) {
@@ -258,8 +286,6 @@ scan_status_t launch(const Call &c, hipStream_t stream, Workspace *ws_override, 
   }
   a.exclusive = (c.flags & SCAN_EXCLUSIVE) ? 1u : 0u;
   a.reverse = (c.flags & SCAN_REVERSE) ? 1u : 0u;
-  a.vec_in = ((uintptr_t)c.in & 15u) == 0;
-  a.vec_out = ((uintptr_t)c.out & 15u) == 0;
 
   const int threads = sh.block;
   int64_t grid = T;
@@ -267,17 +293,17 @@ scan_status_t launch(const Call &c, hipStream_t stream, Workspace *ws_override, 
   a.ordered = 0u;
   a.pubcnt = ws ? ws->pubcnt : nullptr;
   bool cooperative = false;
-  if (T > 1 && cf.mode == kModeOrdered) {
+  if (T > 1 && mode == kModeOrdered) {
     a.ordered = 1u;
     a.total_acquires = 0;
-  } else if (T > 1 && cf.mode == kModeStatic) {
-    grid = std::min<int64_t>(T, resident_blocks(fn, threads, di.cus));
+  } else if (T > 1 && mode == kModeStatic) {
+    grid = std::min<int64_t>(T, resident_grid(fn, threads, di.cus, per_cu, cu_pct));
     a.one_tile = 0u;
     a.stride = (uint32_t)grid;
     a.total_acquires = 0;
     cooperative = true;
-  } else if (T > 1 && cf.mode == kModePersistent) {
-    grid = std::min<int64_t>(T, resident_blocks(fn, threads, di.cus));
+  } else if (T > 1 && mode == kModePersistent) {
+    grid = std::min<int64_t>(T, resident_grid(fn, threads, di.cus, per_cu, cu_pct));
     a.one_tile = grid == T ? 1u : 0u;
     a.total_acquires = a.one_tile ? (uint64_t)T : (uint64_t)(T + grid);
   } else {
@@ -639,13 +665,15 @@ scan_status_t scan_segmented_looped(const void *in, void *out, const int64_t *ho
 int32_t scan_num_configs(void) { return kNumConfigs; }
 
 scan_status_t scan_config_info(int32_t config, int32_t *block, int32_t *items, int32_t *nontemporal,
-                               int32_t *mode) {
+                               int32_t *mode, int32_t *per_cu, int32_t *cu_pct) {
   if (config < 0 || config >= kNumConfigs) return SCAN_ERROR_INVALID_VALUE;
   const KernelShape &sh = kShapes[kConfigs[config].shape];
   if (block) *block = sh.block;
   if (items) *items = sh.items;
   if (nontemporal) *nontemporal = sh.nontemporal;
   if (mode) *mode = kConfigs[config].mode;
+  if (per_cu) *per_cu = kConfigs[config].per_cu;
+  if (cu_pct) *cu_pct = kConfigs[config].cu_pct;
   return SCAN_SUCCESS;
 }
 

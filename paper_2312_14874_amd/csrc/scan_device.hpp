@@ -77,17 +77,6 @@ struct OpsF32 {
 // ------------------------------------------------------------ memory helpers
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-template <bool NT>
-__device__ __forceinline__ u32x4 load4(const uint32_t *p) {
-  if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
-  else return *reinterpret_cast<const u32x4 *>(p);
-}
-template <bool NT>
-__device__ __forceinline__ void store4(uint32_t *p, u32x4 v) {
-  if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(p));
-  else *reinterpret_cast<u32x4 *>(p) = v;
-}
-
 __device__ __forceinline__ uint64_t ld_agent(const uint64_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -162,6 +151,16 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
 }
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// The thread index as a value the compiler cannot see through: per-lane
+// addresses built from it at a use site stay there instead of being hoisted
+// out of the tile loop, where they would hold registers (or spill) for the
+// whole kernel although only rare paths and the look-back need them.
+__device__ __forceinline__ uint32_t opaque_tid() {
+  uint32_t x = threadIdx.x;
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 // ------------------------------------------------------------------ look-back
 // Run by one whole wave.  Lane l, slot k inspects predecessor base-(64k+l)
 // (distance d = 64k+l from tile t = base+1).  dP = nearest PREFIX, dE =
@@ -173,13 +172,15 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_bal
 // left-to-right chain.
 
 // Issue the loads of one window (indices below 0 read as an empty PREFIX).
+// Tile indices are below 2^30 (checked by the host), so they and the byte
+// offsets into the status array fit in 32 bits.
 template <class Op, int K>
-__device__ __forceinline__ void lb_window(const uint64_t *st, int64_t base, uint64_t (&w)[K]) {
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void lb_window(const uint64_t *st, int32_t base, uint64_t (&w)[K]) {
+  const int lane = (int)(opaque_tid() & 63u);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int64_t idx = base - (int64_t)(64 * k + lane);
-    w[k] = idx >= 0 ? ld_agent(st + idx) : Op::pack(Op::czero(), kPrefix);
+    const int32_t idx = base - (64 * k + lane);
+    w[k] = idx >= 0 ? ld_agent(st + (uint32_t)idx) : Op::pack(Op::czero(), kPrefix);
   }
 }
 
@@ -189,9 +190,9 @@ template <class Op, int K>
 __device__ typename Op::carry_t look_back(const uint64_t *st, int64_t t, uint32_t spin_limit,
                                           WsHeader *hdr, uint64_t (&w)[K]) {
   using carry_t = typename Op::carry_t;
-  const int lane = threadIdx.x & 63;
+  const int lane = (int)(opaque_tid() & 63u);
   carry_t acc = Op::czero();
-  int64_t base = t - 1;
+  int32_t base = (int32_t)t - 1;
   uint32_t spins = 0;
   constexpr int kNone = 1 << 30;
   for (bool fresh = true;; fresh = false) {
@@ -257,18 +258,12 @@ __device__ typename Op::carry_t look_back(const uint64_t *st, int64_t t, uint32_
 // Tile addressing.  Logical element e of a tile is physical pb+e going
 // forward and pb+TILE-1-e in reverse (a reverse tile is the same aligned block
 // read back to front).  Wave w owns logical [w*WSPAN, (w+1)*WSPAN); in chunk c
-// lane l holds the 4-group of logical c*256+4l .. c*256+4l+3.  The group's
-// lowest physical index is wave_base + quad_off: wave_base is uniform per
-// wave (scalar registers), quad_off is a small non-negative per-lane offset
-// minus a per-chunk constant, which the compiler folds into the load's
-// immediate offset.
+// lane l holds the 4-group of logical c*256+4l .. c*256+4l+3.  wave_base is
+// the lowest physical element of the wave's span (uniform per wave, kept in
+// scalar registers).
 template <bool REV, int TILE, int WSPAN>
 __device__ __forceinline__ int64_t wave_base(int64_t pb, int wave) {
   return REV ? pb + TILE - (int64_t)WSPAN * (wave + 1) : pb + (int64_t)WSPAN * wave;
-}
-template <bool REV, int WSPAN>
-__device__ __forceinline__ int quad_off(int c, int lane) {
-  return REV ? (WSPAN - 4 - lane * 4) - c * 256 : lane * 4 + c * 256;
 }
 __device__ __forceinline__ int wave_id() {
   return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -277,10 +272,12 @@ __device__ __forceinline__ int wave_id() {
 // Hands the workspace to the next launch: clean the rest of the other status
 // array and flip the parity.  Called once per launch, by a workgroup that
 // knows every workgroup of the launch has already read the parity.
-__device__ __forceinline__ void hand_over(const KernelArgs &a, uint32_t p, uint64_t clear_hi, int tid,
-                                          int nthreads) {
+// Run by nthreads threads: the whole workgroup or one wave (nthreads == 64).
+__device__ __forceinline__ void hand_over(const KernelArgs &a, uint32_t p, uint64_t clear_hi, int nthreads) {
   uint64_t *other = a.status + (1 - p) * a.capacity;
-  for (uint64_t i = (uint64_t)a.tiles + tid; i < clear_hi; i += nthreads) st_agent(other + i, 0ull);
+  const uint32_t me = opaque_tid() % (uint32_t)nthreads;
+  const int tid = (int)me;
+  for (uint64_t i = (uint64_t)a.tiles + me; i < clear_hi; i += nthreads) st_agent(other + i, 0ull);
   if (tid == 0) {
     st_agent(&a.hdr->counter[1 - p], 0ull);
     st_agent(&a.hdr->dirty[1 - p], 0ull);
@@ -336,67 +333,96 @@ __device__ bool mark_heads(const KernelArgs &a, int64_t t, uint32_t *heads, uint
   return *flag != 0u;
 }
 
-// Issue the loads of tile t into R; all are issued before any is used (the
-// branch is outside the chunk loop).  Partial tiles and misaligned inputs take
-// the element-wise path, identity-padded.
-template <class SH, bool NT, bool REV>
-__device__ __forceinline__ void load_tile(const KernelArgs &a, int64_t t, int wave, int lane,
-                                          u32x4 (&R)[SH::CH]) {
-  const int64_t ptile = REV ? (a.tiles - 1 - t) : t;
-  const int64_t pb = ptile * (int64_t)SH::TILE;
-  const int64_t wb = wave_base<REV, SH::TILE, SH::WSPAN>(pb, wave);
-  const uint32_t *wp = static_cast<const uint32_t *>(a.in) + wb;
-  if (pb + SH::TILE <= a.n && a.vec_in) {
-#pragma unroll
-    for (int c = 0; c < SH::CH; ++c) R[c] = load4<NT>(wp + quad_off<REV, SH::WSPAN>(c, lane));
-  } else {
-    // element j of chunk c is valid iff lb + j < lim - coff(c): the
-    // lane-dependent side takes 4 values, the other side is uniform
-    const int64_t remw = a.n - wb;
-    const int lim = remw <= 0 ? 0 : (remw >= SH::WSPAN ? SH::WSPAN : (int)remw);
-    const int lb = quad_off<REV, SH::WSPAN>(0, lane);
-#pragma unroll
-    for (int c = 0; c < SH::CH; ++c) {
-      const int coff = REV ? -c * 256 : c * 256;
-      const int room = lim - coff;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) R[c][j] = (lb + j < room) ? wp[lb + coff + j] : 0u;
-    }
-  }
+// Buffer resource over one wave's span of WSPAN elements starting at p, of
+// which the first `valid` bytes exist (clamped to [0, 4*WSPAN]).  Buffer
+// instructions check every dword against that count (the lane offset plus
+// the immediate; the scalar offset is always 0 here): loads beyond it return
+// 0, the identity of both operators, and stores beyond it are dropped, so
+// ragged tiles need no separate path.  The resource lives in scalar
+// registers.
+template <int WSPAN>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const void *p, int64_t valid) {
+  const int nr = valid <= 0 ? 0 : (valid >= 4 * WSPAN ? 4 * WSPAN : (int)valid);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, nr, 0x00020000);
 }
 
-template <class SH, bool NT, bool REV>
-__device__ __forceinline__ void store_tile(const KernelArgs &a, int64_t t, int wave, int lane,
-                                           u32x4 (&R)[SH::CH]) {
-  const int64_t ptile = REV ? (a.tiles - 1 - t) : t;
-  const int64_t pb = ptile * (int64_t)SH::TILE;
-  const int64_t wb = wave_base<REV, SH::TILE, SH::WSPAN>(pb, wave);
-  uint32_t *wp = static_cast<uint32_t *>(a.out) + wb;
-  if (pb + SH::TILE <= a.n && a.vec_out) {
+// Byte offset of lane l's 4-group of chunk c in its wave's span: forward
+// 1024c + 16l; reverse (chunks from the top of the span down, lanes from the
+// top of the chunk down) 4*WSPAN - 16 - 16l - 1024c.  The per-chunk constant
+// becomes the instruction's immediate offset.
+template <bool REV, int WSPAN>
+__device__ __forceinline__ uint32_t lane_off(int lane) {
+  return REV ? 4u * WSPAN - 16u - 16u * (uint32_t)lane : 16u * (uint32_t)lane;
+}
+template <bool REV>
+__device__ __forceinline__ uint32_t chunk_off(uint32_t lo, int c) {
+  return REV ? lo - 1024u * (uint32_t)c : lo + 1024u * (uint32_t)c;
+}
+
+constexpr int kNtAux = 2;   // cache policy: non-temporal
+
+// Issue the loads of tile t into R; all are issued before any is used.
+// Elements beyond n read as the identity.  VEC: 128-bit accesses (the buffer
+// is 16-byte aligned); otherwise four dword accesses per 4-group, same layout.
+// One wave's view of one tile in a buffer: the resource over the wave's span
+// and the lane's byte offset.  Chunk c of the tile is R[c].
+template <class SH, bool NT, bool REV, bool VEC>
+struct WaveSpan {
+  static constexpr int aux = NT ? kNtAux : 0;
+  __amdgpu_buffer_rsrc_t rs;
+  uint32_t lo;
+  __device__ __forceinline__ WaveSpan(const void *buf, const KernelArgs &a, int64_t t, int wave, int lane) {
+    const int64_t ptile = REV ? (a.tiles - 1 - t) : t;
+    const int64_t wb = wave_base<REV, SH::TILE, SH::WSPAN>(ptile * (int64_t)SH::TILE, wave);
+    rs = span_rsrc<SH::WSPAN>(static_cast<const uint32_t *>(buf) + wb, (a.n - wb) * 4);
+    // recomputed per tile, so neither it nor the chunk offsets are hoisted
+    // out of the tile loop
+    lo = lane_off<REV, SH::WSPAN>((int)(opaque_tid() & 63u));
+    (void)lane;
+  }
+  __device__ __forceinline__ void load(int c, u32x4 &r) const {
+    if constexpr (VEC) {
+      r = __builtin_amdgcn_raw_buffer_load_b128(rs, chunk_off<REV>(lo, c), 0, aux);
+    } else {
 #pragma unroll
-    for (int c = 0; c < SH::CH; ++c) store4<NT>(wp + quad_off<REV, SH::WSPAN>(c, lane), R[c]);
-  } else {
-    const int64_t remw = a.n - wb;
-    const int lim = remw <= 0 ? 0 : (remw >= SH::WSPAN ? SH::WSPAN : (int)remw);
-    const int lb = quad_off<REV, SH::WSPAN>(0, lane);
-#pragma unroll
-    for (int c = 0; c < SH::CH; ++c) {
-      const int coff = REV ? -c * 256 : c * 256;
-      const int room = lim - coff;
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (lb + j < room) wp[lb + coff + j] = R[c][j];
+      for (int k = 0; k < 4; ++k) r[k] = __builtin_amdgcn_raw_buffer_load_b32(rs, chunk_off<REV>(lo, c) + 4u * k, 0, aux);
     }
   }
+  __device__ __forceinline__ void store(int c, const u32x4 &r) const {
+    if constexpr (VEC) {
+      __builtin_amdgcn_raw_buffer_store_b128(r, rs, chunk_off<REV>(lo, c), 0, aux);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) __builtin_amdgcn_raw_buffer_store_b32(r[k], rs, chunk_off<REV>(lo, c) + 4u * k, 0, aux);
+    }
+  }
+};
+
+template <class SH, bool NT, bool REV, bool VEC>
+__device__ __forceinline__ void load_tile(const KernelArgs &a, int64_t t, int wave, int lane,
+                                          u32x4 (&R)[SH::CH]) {
+  const WaveSpan<SH, NT, REV, VEC> in(a.in, a, t, wave, lane);
+#pragma unroll
+  for (int c = 0; c < SH::CH; ++c) in.load(c, R[c]);
+}
+
+template <class SH, bool NT, bool REV, bool VEC>
+__device__ __forceinline__ void store_tile(const KernelArgs &a, int64_t t, int wave, int lane,
+                                           u32x4 (&R)[SH::CH]) {
+  const WaveSpan<SH, NT, REV, VEC> out(a.out, a, t, wave, lane);
+#pragma unroll
+  for (int c = 0; c < SH::CH; ++c) out.store(c, R[c]);
 }
 
 // In-register scan of this wave's span (the 64-lane form of the horizontal
-// in-register scan of Section 3.1, chained over the chunks).  On return
-// R[c][k] holds the wave-local value of logical element k of chunk c
-// (inclusive or exclusive, restarted at segment starts), am[c] (segmented)
-// marks the elements that the carry into the wave still applies to, and
-// (wsum, wflag) is the wave's total (since its last segment start) and
-// whether it contains a start.
+// in-register scan of Section 3.1, chained over the chunks).  Logical element
+// k of a lane's 4-group sits in slot ph(k) of R[c]: slot k going forward,
+// slot 3-k in reverse tiles, so the values never move between slots and the
+// group is stored back as it was loaded.  On return the slot of logical
+// element k of chunk c holds its wave-local value (inclusive or exclusive,
+// restarted at segment starts), am[c] bit k (segmented) marks the elements
+// the carry into the wave still applies to, and (wsum, wflag) is the wave's
+// total (since its last segment start) and whether it contains a start.
 template <class Op, class SH, bool SEG, bool REV>
 __device__ __forceinline__ void scan_wave(uint32_t exclusive, int wave, int lane, bool any_head,
                                           const uint32_t *heads, u32x4 (&R)[SH::CH],
@@ -404,18 +430,13 @@ __device__ __forceinline__ void scan_wave(uint32_t exclusive, int wave, int lane
                                           typename Op::carry_t &wsum_out, uint32_t &wflag_out) {
   using lane_t = typename Op::lane_t;
   using carry_t = typename Op::carry_t;
+  constexpr int p0 = REV ? 3 : 0, p1 = REV ? 2 : 1, p2 = REV ? 1 : 2, p3 = REV ? 0 : 3;
+  constexpr int ph[4] = {p0, p1, p2, p3};
   carry_t wsum = Op::czero();
   uint32_t wflag = 0u;
 #pragma unroll
   for (int c = 0; c < SH::CH; ++c) {
-    if (REV) {
-      const uint32_t x0 = R[c][0], x1 = R[c][1];
-      R[c][0] = R[c][3];
-      R[c][1] = R[c][2];
-      R[c][2] = x1;
-      R[c][3] = x0;
-    }
-    uint32_t hb = 0u;   // segment starts among this lane's 4 elements (bit k)
+    uint32_t hb = 0u;   // segment starts among this lane's 4 elements (bit k = logical k)
     if constexpr (SEG) {
       if (any_head) {
         const int e0 = wave * SH::WSPAN + c * 256 + lane * 4;
@@ -425,11 +446,11 @@ __device__ __forceinline__ void scan_wave(uint32_t exclusive, int wave, int lane
     // in-lane inclusive partials, restarting at segment starts
 #pragma unroll
     for (int k = 1; k < 4; ++k) {
-      const lane_t sum = Op::ladd(Op::lfrom(R[c][k - 1]), Op::lfrom(R[c][k]));
-      if constexpr (SEG) R[c][k] = ((hb >> k) & 1u) ? R[c][k] : Op::lbits(sum);
-      else R[c][k] = Op::lbits(sum);
+      const lane_t sum = Op::ladd(Op::lfrom(R[c][ph[k - 1]]), Op::lfrom(R[c][ph[k]]));
+      if constexpr (SEG) R[c][ph[k]] = ((hb >> k) & 1u) ? R[c][ph[k]] : Op::lbits(sum);
+      else R[c][ph[k]] = Op::lbits(sum);
     }
-    lane_t x = Op::lfrom(R[c][3]);
+    lane_t x = Op::lfrom(R[c][p3]);
     uint32_t f = hb != 0u;
     uint32_t cf = 0u;
     if constexpr (SEG) {
@@ -451,41 +472,47 @@ __device__ __forceinline__ void scan_wave(uint32_t exclusive, int wave, int lane
         for (int k = 3; k >= 0; --k) {
           const uint32_t h = (hb >> k) & 1u;
           const uint32_t before = hb & ((1u << k) - 1u);   // starts strictly before k in the lane
-          const lane_t prev = k ? Op::lfrom(R[c][k - 1]) : Op::lzero();
+          const lane_t prev = k ? Op::lfrom(R[c][ph[k ? k - 1 : 0]]) : Op::lzero();
           const lane_t v = h ? Op::lzero() : (before ? prev : (k ? Op::ladd(lex, prev) : lex));
-          R[c][k] = Op::lbits(v);
+          R[c][ph[k]] = Op::lbits(v);
           m |= (!h && !before && !lexf) ? (1u << k) : 0u;
         }
       } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const uint32_t seen = hb & ((2u << k) - 1u);      // starts at or before k
-          if (!seen) R[c][k] = Op::lbits(Op::ladd(lex, Op::lfrom(R[c][k])));
+          if (!seen) R[c][ph[k]] = Op::lbits(Op::ladd(lex, Op::lfrom(R[c][ph[k]])));
           m |= (!seen && !lexf) ? (1u << k) : 0u;
         }
       }
     } else {
-      if (exclusive) {
-        R[c][3] = Op::lbits(Op::ladd(lex, Op::lfrom(R[c][2])));
-        R[c][2] = Op::lbits(Op::ladd(lex, Op::lfrom(R[c][1])));
-        R[c][1] = Op::lbits(Op::ladd(lex, Op::lfrom(R[c][0])));
-        R[c][0] = Op::lbits(lex);
-      } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) R[c][k] = Op::lbits(Op::ladd(lex, Op::lfrom(R[c][k])));
-      }
+      // the chunk's prefix within the wave (uniform) joins the lane's offset;
+      // inclusive: off + p_k, exclusive: off + p_{k-1}, chosen by selects so
+      // every chunk stays in its own registers
+      const lane_t off = c > 0 ? Op::ladd(Op::narrow(wsum), lex) : lex;
+      const bool ex = exclusive != 0u;
+      R[c][p3] = Op::lbits(Op::ladd(off, Op::lfrom(ex ? R[c][p2] : R[c][p3])));
+      R[c][p2] = Op::lbits(Op::ladd(off, Op::lfrom(ex ? R[c][p1] : R[c][p2])));
+      R[c][p1] = Op::lbits(Op::ladd(off, Op::lfrom(ex ? R[c][p0] : R[c][p1])));
+      R[c][p0] = ex ? Op::lbits(off) : Op::lbits(Op::ladd(off, Op::lfrom(R[c][p0])));
     }
-    // fold the chunk's prefix within the wave (uniform) into its elements
-    if (c > 0) {
+    // segmented: fold the chunk's prefix within the wave (uniform) into the
+    // elements it applies to
+    if (SEG && c > 0) {
       const lane_t cp = Op::narrow(wsum);
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        if ((m >> k) & 1u) R[c][k] = Op::lbits(Op::ladd(cp, Op::lfrom(R[c][k])));
+        if ((m >> k) & 1u) R[c][ph[k]] = Op::lbits(Op::ladd(cp, Op::lfrom(R[c][ph[k]])));
       if (wflag) m = 0u;   // a segment started in an earlier chunk of this wave
     }
     if constexpr (SEG) am[c] = m;
     wsum = cf ? Op::widen(ct) : Op::cadd(wsum, Op::widen(ct));
     wflag |= cf;
+    // finish the chunk in its own registers now: without this the compiler
+    // defers the lane-offset add to the final carry add (one three-operand
+    // add per element), keeping one offset register per chunk alive through
+    // the look-back
+    asm volatile("" : "+v"(R[c]));
   }
   wsum_out = wsum;
   wflag_out = wflag;
@@ -536,27 +563,32 @@ __device__ __forceinline__ void publish_first(uint64_t *st, int64_t t, typename 
   }
 }
 
-// Add the carry into each wave and store.  out = win + R where the carry
-// applies (every element unless segmented).
-template <class Op, class SH, bool SEG, bool NT, bool REV>
-__device__ __forceinline__ void finish_tile(const KernelArgs &a, int64_t t, int wave, int lane,
-                                            typename Op::carry_t win, u32x4 (&R)[SH::CH],
+// Add the carry into the wave's values: R = win + R where the carry applies
+// (every element unless segmented; am[c] bit k is logical element k, in slot
+// 3-k of reverse tiles).
+template <class Op, class SH, bool SEG, bool REV>
+__device__ __forceinline__ void apply_carry(typename Op::carry_t win, u32x4 (&R)[SH::CH],
                                             const uint32_t (&am)[SEG ? SH::CH : 1]) {
   using lane_t = typename Op::lane_t;
   const lane_t w32 = Op::narrow(win);
 #pragma unroll
   for (int c = 0; c < SH::CH; ++c) {
-    lane_t o[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const lane_t l = Op::lfrom(R[c][k]);
-      if constexpr (SEG) o[k] = ((am[c] >> k) & 1u) ? Op::ladd(w32, l) : l;
-      else o[k] = Op::ladd(w32, l);
+      const int slot = REV ? 3 - k : k;
+      const lane_t l = Op::lfrom(R[c][slot]);
+      if constexpr (SEG) R[c][slot] = Op::lbits(((am[c] >> k) & 1u) ? Op::ladd(w32, l) : l);
+      else R[c][slot] = Op::lbits(Op::ladd(w32, l));
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) R[c][k] = Op::lbits(REV ? o[3 - k] : o[k]);
   }
-  store_tile<SH, NT, REV>(a, t, wave, lane, R);
+}
+
+template <class Op, class SH, bool SEG, bool NT, bool REV, bool VEC>
+__device__ __forceinline__ void finish_tile(const KernelArgs &a, int64_t t, int wave, int lane,
+                                            typename Op::carry_t win, u32x4 (&R)[SH::CH],
+                                            const uint32_t (&am)[SEG ? SH::CH : 1]) {
+  apply_carry<Op, SH, SEG, REV>(win, R, am);
+  store_tile<SH, NT, REV, VEC>(a, t, wave, lane, R);
 }
 
 // End of a workgroup in a static round-robin launch: count it; the last
@@ -573,94 +605,107 @@ __device__ __forceinline__ void static_done(const KernelArgs &a, uint32_t parity
     if (*flag) *clear_hi = ld_agent(&a.hdr->dirty[1 - parity]);
   }
   __syncthreads();
-  if (*flag) hand_over(a, parity, *clear_hi, tid, nthreads);
+  if (*flag) hand_over(a, parity, *clear_hi, nthreads);
 }
 
 // ------------------------------------------------------------------- kernels
-// One tile per workgroup iteration.  Tile numbers come either from the device
-// counter (dynamic: any workgroup that waits depends only on workgroups that
-// are already running) or, with `ordered`, from blockIdx.x (no counter; this
-// relies on the dispatcher starting workgroups in index order, so a
-// workgroup's predecessors have all been started before it).
-template <class Op, int BLOCK, int ITEMS, bool SEG, bool NT, bool REV>
-__global__ void __launch_bounds__(BLOCK) scan_tiles(KernelArgs a) {
+// Counter modes: take the next tile from the device counter.  Run by one
+// whole wave; the result is uniform (>= tiles when none is left).  The
+// launch's last increment hands the workspace over: every workgroup has read
+// the parity before its first increment.
+__device__ __forceinline__ int64_t acquire_tile(const KernelArgs &a, uint32_t parity, int lane) {
+  uint64_t tk = 0, clear_hi = 0;
+  uint32_t last = 0;
+  if (lane == 0) {
+    tk = __hip_atomic_fetch_add(&a.hdr->counter[parity], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    last = tk == a.total_acquires - 1;
+    if (tk < (uint64_t)a.tiles) st_agent(a.status + (1 - parity) * a.capacity + tk, 0ull);
+    if (last) clear_hi = ld_agent(&a.hdr->dirty[1 - parity]);
+  }
+  tk = readlane64(tk, 0);
+  if (readlane32(last, 0)) hand_over(a, parity, readlane64(clear_hi, 0), 64);
+  return (int64_t)tk;
+}
+
+// One tile per workgroup iteration.  Tile numbers come from the device counter
+// (dynamic: any workgroup that waits depends only on workgroups that are
+// already running), from blockIdx.x with `ordered` (no counter; this relies
+// on the dispatcher starting workgroups in index order, so a workgroup's
+// predecessors have all been started before it), or round robin over a
+// co-resident grid with `stride`.  A resident workgroup takes its next tile
+// only when it is ready to load it (after its look-back): tiles then start
+// close to index order, which keeps the look-back waits short (taking the
+// next tile earlier, during the look-back, measured slower).  The next tile's
+// loads are issued between the current tile's stores, into the registers
+// each store frees.  Shared-memory values alternate between two slots per
+// iteration, so consecutive tiles need no barrier between them.
+// MINW: waves per SIMD the register allocation must allow (the number of
+// workgroups of 4 waves resident per CU).
+template <class Op, int BLOCK, int ITEMS, bool SEG, bool NT, bool REV, bool VEC, int MINW>
+__global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
   using SH = Shape<BLOCK, ITEMS>;
   constexpr int K = 4;   // look-back window = 64*K tiles per poll
   using carry_t = typename Op::carry_t;
 
-  __shared__ carry_t s_wtot[SH::WAVES];
-  __shared__ uint32_t s_wflag[SH::WAVES];
-  __shared__ carry_t s_carry;
-  __shared__ uint64_t s_tile;
+  __shared__ carry_t s_wtot[2][SH::WAVES];
+  __shared__ uint32_t s_wflag[2][SH::WAVES];
+  __shared__ carry_t s_carry[2];
+  __shared__ int64_t s_tile[2];
   __shared__ uint64_t s_clear_hi;
-  __shared__ uint32_t s_parity, s_last, s_flag;
+  __shared__ uint32_t s_parity, s_flag;
   __shared__ uint32_t s_heads[SEG ? SH::TILE / 32 : 1];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = wave_id();
   const bool multi = a.tiles > 1;
+  const bool counter = multi && !a.ordered && !a.stride;
+  const bool resident = counter && !a.one_tile;
   uint32_t parity = 0;
 
-  for (int iter = 0;; ++iter) {
-    // ------------------------------------------------ acquire a tile
-    int64_t t;
-    if (!multi) {
-      if (iter > 0) break;
-      t = 0;
-    } else if (a.ordered) {
-      if (iter > 0) break;
-      t = blockIdx.x;
-      if (tid == 0) {
-        parity = ld_agent32(&a.hdr->parity);
-        st_agent(a.status + (1 - parity) * a.capacity + t, 0ull);
+  // ------------------------------------------------ first tile
+  int64_t t = 0;
+  if (multi) {
+    if (wave == 0) {
+      parity = readlane32(lane == 0 ? ld_agent32(&a.hdr->parity) : 0u, 0);
+      if (a.ordered) {
+        t = blockIdx.x;
+        if (lane == 0) {
+          st_agent(a.status + (1 - parity) * a.capacity + t, 0ull);
+          s_clear_hi = (t == a.tiles - 1) ? ld_agent(&a.hdr->dirty[1 - parity]) : 0ull;
+        }
+      } else if (a.stride) {
+        t = blockIdx.x;
+      } else {
+        t = acquire_tile(a, parity, lane);
+      }
+      if (lane == 0) {
         s_parity = parity;
-        s_clear_hi = (t == a.tiles - 1) ? ld_agent(&a.hdr->dirty[1 - parity]) : 0ull;
+        s_tile[0] = t;
       }
-      __syncthreads();
-      parity = s_parity;
-    } else if (a.stride) {
-      // static round robin over a co-resident grid
-      t = (int64_t)blockIdx.x + (int64_t)iter * a.stride;
-      if (iter == 0) {
-        if (tid == 0) s_parity = ld_agent32(&a.hdr->parity);
-        __syncthreads();
-        parity = s_parity;
-      }
-      if (t >= a.tiles) break;
-      if (tid == 0) st_agent(a.status + (1 - parity) * a.capacity + t, 0ull);
-    } else {
-      if (tid == 0) {
-        if (iter == 0) parity = ld_agent32(&a.hdr->parity);
-        const uint64_t tk = __hip_atomic_fetch_add(&a.hdr->counter[parity], 1ull,
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t last = tk == a.total_acquires - 1;
-        if (tk < (uint64_t)a.tiles) st_agent(a.status + (1 - parity) * a.capacity + tk, 0ull);
-        s_clear_hi = last ? ld_agent(&a.hdr->dirty[1 - parity]) : 0ull;
-        s_tile = tk;
-        s_parity = parity;
-        s_last = last;
-      }
-      __syncthreads();
-      t = (int64_t)s_tile;
-      const uint32_t p = s_parity;
-      // last increment of this launch: every workgroup has read the parity
-      if (s_last) hand_over(a, p, s_clear_hi, tid, BLOCK);
-      if (t >= a.tiles) break;
-      parity = p;
     }
+    __syncthreads();
+    parity = s_parity;
+    t = s_tile[0];
+  }
+
+  u32x4 R[SH::CH];
+  if (t < a.tiles) load_tile<SH, NT, REV, VEC>(a, t, wave, lane, R);
+
+  for (int it = 0;; ++it) {
+    const int slot = it & 1;
+    if (t >= a.tiles) break;
+    if (a.stride && tid == 0) st_agent(a.status + (1 - parity) * a.capacity + t, 0ull);
 
     bool any_head = false;
     if constexpr (SEG) any_head = mark_heads<BLOCK, SH::TILE, REV>(a, t, s_heads, &s_flag);
 
-    // load once, scan in registers, combine the waves
-    u32x4 R[SH::CH];
+    // the tile's loads are in flight: scan in registers, combine the waves
     uint32_t am[SEG ? SH::CH : 1];
-    load_tile<SH, NT, REV>(a, t, wave, lane, R);
     carry_t wsum, wpre, agg;
     uint32_t wflag, wpref, aggf;
     scan_wave<Op, SH, SEG, REV>(a.exclusive, wave, lane, any_head, s_heads, R, am, wsum, wflag);
-    combine_waves<Op, SH::WAVES>(wave, lane, wsum, wflag, s_wtot, s_wflag, wpre, wpref, agg, aggf);
+    combine_waves<Op, SH::WAVES>(wave, lane, wsum, wflag, s_wtot[slot], s_wflag[slot], wpre, wpref, agg, aggf);
 
     // publish, look back, publish the prefix
     bool first_is_head = false;
@@ -675,25 +720,56 @@ __global__ void __launch_bounds__(BLOCK) scan_tiles(KernelArgs a) {
       carry_t carry = Op::czero();
       if (need_carry) {
         uint64_t w[K];
-        lb_window<Op, K>(st, t - 1, w);
+        lb_window<Op, K>(st, (int32_t)t - 1, w);
         carry = look_back<Op, K>(st, t, a.spin_limit, a.hdr, w);
         if (!aggf && lane == 0)
           st_agent(st + t, Op::pack(Op::canon(Op::cadd(carry, Op::canon(agg))), kPrefix));
       }
-      if (lane == 0) s_carry = carry;
+      if (lane == 0) s_carry[slot] = carry;
     }
     __syncthreads();
-    const carry_t carry = need_carry ? s_carry : Op::czero();
+    const carry_t carry = need_carry ? s_carry[slot] : Op::czero();
+    apply_carry<Op, SH, SEG, REV>(wpref ? wpre : Op::cadd(carry, wpre), R, am);
 
-    // add the carry and store once
-    finish_tile<Op, SH, SEG, NT, REV>(a, t, wave, lane, wpref ? wpre : Op::cadd(carry, wpre), R, am);
+    // Store the tile and load the next one into the same registers: the
+    // first half of the stores goes out while the next tile is taken from the
+    // counter; then each further store frees a chunk that the next tile's
+    // load fills at once, so reads and writes share the CU's memory
+    // pipeline instead of alternating.
+    constexpr int KH = SH::CH / 2;
+    const WaveSpan<SH, NT, REV, VEC> out(a.out, a, t, wave, lane);
+#pragma unroll
+    for (int c = 0; c < KH; ++c) out.store(c, R[c]);
+    int64_t next = a.stride ? t + a.stride : a.tiles;
+    if (resident) {
+      if (wave == 0) {
+        const int64_t tk = acquire_tile(a, parity, lane);
+        if (lane == 0) s_tile[slot ^ 1] = tk;
+      }
+      __syncthreads();
+      next = s_tile[slot ^ 1];
+    }
+    if (next < a.tiles) {
+      const WaveSpan<SH, NT, REV, VEC> in(a.in, a, next, wave, lane);
+#pragma unroll
+      for (int c = KH; c < SH::CH; ++c) {
+        out.store(c, R[c]);
+        in.load(c - KH, R[c - KH]);
+      }
+#pragma unroll
+      for (int c = SH::CH - KH; c < SH::CH; ++c) in.load(c, R[c]);
+    } else {
+#pragma unroll
+      for (int c = KH; c < SH::CH; ++c) out.store(c, R[c]);
+    }
 
     if (multi && a.ordered) {
       if (t == a.tiles - 1) {
         // wait until every other tile has published (so every workgroup of
         // the launch has read the parity), then hand the workspace over
         if (wave == 0) {
-          const uint64_t *cnt = a.pubcnt + (parity * kPubSlots + lane) * kPubStride;
+          const uint32_t l = opaque_tid() & 63u;
+          const uint64_t *cnt = a.pubcnt + (parity * kPubSlots + l) * kPubStride;
           for (uint32_t spins = 0;; ++spins) {
             uint32_t c = (uint32_t)ld_agent(cnt);
             c = readlane32(wave_scan<OpsU32>(c), 63);
@@ -705,15 +781,14 @@ __global__ void __launch_bounds__(BLOCK) scan_tiles(KernelArgs a) {
             __builtin_amdgcn_s_sleep(1);
           }
           // the next launch uses the other parity's counters
-          st_agent(a.pubcnt + ((1 - parity) * kPubSlots + lane) * kPubStride, 0ull);
+          st_agent(a.pubcnt + ((1 - parity) * kPubSlots + l) * kPubStride, 0ull);
         }
         __syncthreads();
-        hand_over(a, parity, s_clear_hi, tid, BLOCK);
+        hand_over(a, parity, s_clear_hi, BLOCK);
       }
       break;
     }
-    if (a.one_tile || !multi) break;
-    __syncthreads();   // LDS is reused by the next tile
+    t = next;
   }
   if (multi && a.stride) static_done(a, parity, tid, BLOCK, &s_flag, &s_clear_hi);
 }

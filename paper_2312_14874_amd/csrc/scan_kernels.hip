@@ -5,34 +5,54 @@
 
 namespace mi355scan {
 
-#define MI355SCAN_FNS(KER, B, I, NT)                                                        \
-  {{{(const void *)&KER<OpsU32, B, I, false, (NT != 0), false>,                             \
-     (const void *)&KER<OpsU32, B, I, false, (NT != 0), true>},                             \
-    {(const void *)&KER<OpsU32, B, I, true, (NT != 0), false>,                              \
-     (const void *)&KER<OpsU32, B, I, true, (NT != 0), true>}},                             \
-   {{(const void *)&KER<OpsF32, B, I, false, (NT != 0), false>,                             \
-     (const void *)&KER<OpsF32, B, I, false, (NT != 0), true>},                             \
-    {(const void *)&KER<OpsF32, B, I, true, (NT != 0), false>,                              \
-     (const void *)&KER<OpsF32, B, I, true, (NT != 0), true>}}}
+// W[op][seg]: waves per SIMD the register allocation targets (per shape,
+// the most at which the flat variants do not spill).  Workgroups of 768 and
+// 1024 threads need 3 and 4 waves per SIMD to fit at all; some of their
+// reverse and segmented variants spill a few registers on rare paths.
+#define MI355SCAN_FNS(B, I, NT, VEC, WUF, WFF, WUS, WFS)                                      \
+  {{{(const void *)&scan_tiles<OpsU32, B, I, false, (NT != 0), false, VEC, WUF>,               \
+     (const void *)&scan_tiles<OpsU32, B, I, false, (NT != 0), true, VEC, WUF>},               \
+    {(const void *)&scan_tiles<OpsU32, B, I, true, (NT != 0), false, VEC, WUS>,                \
+     (const void *)&scan_tiles<OpsU32, B, I, true, (NT != 0), true, VEC, WUS>}},               \
+   {{(const void *)&scan_tiles<OpsF32, B, I, false, (NT != 0), false, VEC, WFF>,               \
+     (const void *)&scan_tiles<OpsF32, B, I, false, (NT != 0), true, VEC, WFF>},               \
+    {(const void *)&scan_tiles<OpsF32, B, I, true, (NT != 0), false, VEC, WFS>,                \
+     (const void *)&scan_tiles<OpsF32, B, I, true, (NT != 0), true, VEC, WFS>}}}
 
-#define MI355SCAN_TILES(B, I, NT) {B, I, NT, MI355SCAN_FNS(scan_tiles, B, I, NT)}
+// {block, items, nontemporal, waves per SIMD: u32 flat, f32 flat, u32 segmented, f32 segmented}
+#define MI355SCAN_TILES(B, I, NT, WUF, WFF, WUS, WFS) \
+  {B, I, NT, MI355SCAN_FNS(B, I, NT, true, WUF, WFF, WUS, WFS)}
 
 const KernelShape kShapes[] = {
-    MI355SCAN_TILES(256, 16, 1),     // 0
-    MI355SCAN_TILES(256, 32, 1),     // 1
-    MI355SCAN_TILES(256, 64, 1),     // 2
-    MI355SCAN_TILES(256, 96, 1),     // 3
-    MI355SCAN_TILES(256, 128, 1),    // 4
-    MI355SCAN_TILES(512, 64, 1),     // 5
+    MI355SCAN_TILES(256, 16, 1, 7, 6, 5, 5),      // 0
+    MI355SCAN_TILES(256, 32, 1, 6, 5, 5, 3),      // 1
+    MI355SCAN_TILES(256, 64, 1, 3, 3, 3, 3),      // 2
+    MI355SCAN_TILES(256, 96, 1, 3, 2, 2, 2),      // 3
+    MI355SCAN_TILES(256, 128, 1, 2, 2, 2, 2),     // 4
+    MI355SCAN_TILES(512, 64, 1, 4, 2, 2, 2),      // 5
+    MI355SCAN_TILES(512, 128, 1, 2, 2, 2, 2),     // 6
+    MI355SCAN_TILES(1024, 64, 1, 4, 4, 4, 4),     // 7
+    MI355SCAN_TILES(768, 128, 1, 3, 3, 3, 3),     // 8
 };
 const int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
-// {shape, mode}: see TileMode.
+// Inputs or outputs that are not 16-byte aligned: dword accesses.
+const KernelShape kUnalignedShape = {256, 32, 1, MI355SCAN_FNS(256, 32, 1, false, 4, 4, 3, 3)};
+
+// {shape, mode, workgroups per CU, percent of CUs}: see TileMode and Config.
 const Config kConfigs[] = {
-    {0, 2}, {1, 2}, {2, 2}, {3, 2}, {4, 2}, {5, 2},   // 0-5   tile = workgroup index
-    {4, 1}, {2, 1},                                   // 6-7   resident grid, tiles from the counter
-    {2, 4}, {4, 4}, {5, 4},                           // 8-10  resident grid, static round robin
-    {0, 0},                                           // 11    one tile per workgroup from the counter
+    {0, 2, 0, 100}, {1, 2, 0, 100}, {2, 2, 0, 100},   // 0-5   tile = workgroup index
+    {3, 2, 0, 100}, {4, 2, 0, 100}, {5, 2, 0, 100},
+    {4, 1, 0, 100}, {2, 1, 0, 100},                   // 6-7   resident grid, tiles from the counter
+    {2, 4, 0, 100}, {4, 4, 0, 100}, {5, 4, 0, 100},   // 8-10  resident grid, static round robin
+    {0, 0, 0, 100},                                   // 11    one tile per workgroup from the counter
+    {4, 1, 1, 100}, {4, 1, 2, 100}, {2, 1, 2, 100},   // 12-19 resident grids of fewer workgroups
+    {2, 1, 3, 100}, {5, 1, 1, 100}, {3, 1, 2, 100},
+    {4, 4, 2, 100}, {2, 4, 3, 100},
+    {6, 1, 1, 100}, {7, 1, 1, 100}, {8, 1, 1, 100},   // 20-22 one big workgroup per CU
+    {2, 1, 1, 100}, {3, 1, 1, 100},                   // 23-24
+    {6, 4, 1, 100}, {8, 4, 1, 100},                   // 25-26 static round robin, one per CU
+    {8, 1, 1, 75}, {8, 1, 1, 88}, {6, 1, 1, 75},      // 27-29 one per CU on part of the CUs
 };
 const int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 

@@ -43,8 +43,6 @@ struct KernelArgs {
   uint32_t spin_limit;
   uint32_t exclusive;
   uint32_t reverse;
-  uint32_t vec_in;            // in is 16-byte aligned
-  uint32_t vec_out;           // out is 16-byte aligned
   uint32_t one_tile;          // every workgroup takes exactly one tile
   uint32_t ordered;           // tile = blockIdx.x (no counter; relies on in-order dispatch)
   uint32_t stride;            // static round robin: workgroup b takes tiles b, b+stride, ... (co-resident grid)

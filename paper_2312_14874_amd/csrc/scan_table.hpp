@@ -21,10 +21,13 @@ enum TileMode {
 struct Config {
   int shape;         // index into kShapes
   int mode;          // TileMode
+  int per_cu;        // resident-grid modes: workgroups per CU (0 = as many as fit)
+  int cu_pct;        // resident-grid modes: percent of the CUs the grid covers
 };
 
 extern const KernelShape kShapes[];
 extern const int kNumShapes;
+extern const KernelShape kUnalignedShape;   // dword accesses, for buffers not 16-byte aligned
 extern const Config kConfigs[];
 extern const int kNumConfigs;
 extern const void *kTileSegmentMap;   // the tile -> first segment kernel

@@ -201,10 +201,11 @@ def num_configs() -> int:
 
 
 def config_info(cfg: int) -> dict:
-    b, i, nt, p = (ctypes.c_int32() for _ in range(4))
-    check(lib.scan_config_info(cfg, ctypes.byref(b), ctypes.byref(i), ctypes.byref(nt), ctypes.byref(p)))
+    b, i, nt, p, pc, sg = (ctypes.c_int32() for _ in range(6))
+    check(lib.scan_config_info(cfg, ctypes.byref(b), ctypes.byref(i), ctypes.byref(nt), ctypes.byref(p),
+                               ctypes.byref(pc), ctypes.byref(sg)))
     return {"config": cfg, "block": b.value, "items": i.value, "nontemporal": nt.value,
-            "mode": p.value, "tile": b.value * i.value}
+            "mode": p.value, "per_cu": pc.value, "cu_pct": sg.value, "tile": b.value * i.value}
 
 
 def force_config(cfg: int = -1) -> None:

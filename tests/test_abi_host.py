@@ -79,7 +79,7 @@ def test_other_argument_errors():
     assert L.lib.scan_graph_launch(None, None) == INVALID
     assert L.lib.scan_graph_destroy(None) == INVALID
     assert L.lib.scan_force_config(10_000) == INVALID
-    assert L.lib.scan_config_info(-1, None, None, None, None) == INVALID
+    assert L.lib.scan_config_info(-1, None, None, None, None, None, None) == INVALID
     assert L.lib.scan_segmented_looped(4096, 8192, None, 2, 0, 0, None) == INVALID
     h = ctypes.c_void_p()
     assert L.lib.scan_looped_graph_create(4096, 8192, None, 2, 0, 0, None, ctypes.byref(h)) == INVALID
@@ -92,7 +92,8 @@ def test_configs_are_well_formed():
     for c in range(n):
         info = config_info(c)
         assert info["block"] % 64 == 0 and info["items"] % 4 == 0
-        assert 2048 <= info["tile"] <= 65536 and info["mode"] in (0, 1, 2, 3, 4, 5)
+        assert 2048 <= info["tile"] <= 131072 and info["mode"] in (0, 1, 2, 4)
+        assert info["per_cu"] >= 0 and 1 <= info["cu_pct"] <= 100
 
 
 def test_tune_file_roundtrip(tmp_path):
