@@ -33,6 +33,12 @@ struct OpsU32 {
   using lane_t = uint32_t;    // per-lane arithmetic (up to 256-element chunks)
   using carry_t = uint32_t;   // chunk, wave, tile and inter-tile arithmetic
   static constexpr bool kExact = true;
+  // segmented scans: chunks per plain/segmented branch group, and whether a
+  // wave without a segment start takes a separate select-free carry add
+  // (both chosen by measurement; the float64 carries of OpsF32 need more
+  // registers, so it branches in smaller groups and keeps one carry add)
+  static constexpr int kSegGroup = 4;
+  static constexpr bool kSplitCarry = true;
   __device__ static lane_t lzero() { return 0u; }
   __device__ static carry_t czero() { return 0u; }
   __device__ static lane_t ladd(lane_t a, lane_t b) { return a + b; }
@@ -58,6 +64,8 @@ struct OpsF32 {
   using lane_t = float;
   using carry_t = double;
   static constexpr bool kExact = false;
+  static constexpr int kSegGroup = 2;
+  static constexpr bool kSplitCarry = false;
   __device__ static lane_t lzero() { return 0.0f; }
   __device__ static carry_t czero() { return 0.0; }
   __device__ static lane_t ladd(lane_t a, lane_t b) { return a + b; }
@@ -298,39 +306,87 @@ struct Shape {
 };
 
 // ---------------------------------------------------------------- tile steps
+// Read-only views of the segment map and the offsets through the constant
+// address space: a load from it with a wave-uniform address is a scalar
+// (SMEM) load, counted apart from the vector loads, so it returns while the
+// tile's data is still in flight.  Both arrays are read-only for the whole
+// launch (the map is written by the launch before).
+typedef const __attribute__((address_space(4))) uint32_t k_u32;
+typedef const __attribute__((address_space(4))) int64_t k_i64;
+
 // Segment starts of tile t as an LDS bitmap (TILE bits, logical order).  Whole
-// workgroup (contains barriers).  Returns whether any start was marked.
-template <int BLOCK, int TILE, bool REV>
-__device__ bool mark_heads(const KernelArgs &a, int64_t t, uint32_t *heads, uint32_t *flag) {
+// workgroup (contains barriers).  Returns the waves whose span (WSPAN
+// logical elements each) holds a start, bit w for wave w; the bitmap is
+// written only when that is not zero.  A tile with at most kScalarHeads
+// candidate starts (the common case: segments longer than a tile) reads them
+// with scalar loads and one lane sets the bits; a tile with more falls back
+// to vector loads spread over the workgroup.
+template <int BLOCK, int TILE, int WSPAN, bool REV>
+__device__ uint32_t mark_heads(const KernelArgs &a, int64_t t, uint32_t *heads, uint32_t *flag) {
+  constexpr int kScalarHeads = 8;
   const int tid = threadIdx.x;
-  const int64_t ptile = REV ? (a.tiles - 1 - t) : t;
-  const int64_t pb = ptile * (int64_t)TILE;
+  // tiles < 2^29, so the uniform tile index fits one scalar register
+  const int pt = __builtin_amdgcn_readfirstlane((int)(REV ? (a.tiles - 1 - t) : t));
+  const int64_t pb = (int64_t)pt * TILE;
   const int64_t rem = a.n - pb;
   const int valid = rem < TILE ? (int)rem : TILE;
+  const int shift = REV ? 1 : 0;
   int64_t s_lo, s_hi;
   if (a.tile_seg) {
-    s_lo = a.tile_seg[ptile];
-    s_hi = a.tile_seg[ptile + 1];
+    s_lo = ((k_u32 *)a.tile_seg)[pt];
+    s_hi = ((k_u32 *)a.tile_seg)[pt + 1];
   } else {
     s_lo = 0;
     s_hi = a.num_segments + 1;
   }
-  if (s_hi <= s_lo) return false;
+  if (s_hi <= s_lo) return 0u;
+  const int64_t cnt = s_hi - s_lo;
+  if (a.tile_seg && cnt <= kScalarHeads) {
+    // indices clamped into [s_lo, s_hi - 1] so every load stays inside offsets[0..S]
+    int64_t o[kScalarHeads];
+#pragma unroll
+    for (int k = 0; k < kScalarHeads; ++k) o[k] = ((k_i64 *)a.offsets)[s_lo + (k < cnt ? k : cnt - 1)];
+    uint32_t waves = 0u;
+#pragma unroll
+    for (int k = 0; k < kScalarHeads; ++k) {
+      const int64_t s = s_lo + k;
+      const int64_t ph = o[k] - shift;
+      if (k < cnt && (REV ? (s >= 1) : (s < a.num_segments)) && ph >= pb && ph < pb + valid) {
+        const int e = REV ? (TILE - 1 - (int)(ph - pb)) : (int)(ph - pb);
+        waves |= 1u << (e / WSPAN);
+      }
+    }
+    if (!waves) return 0u;
+    for (int i = tid; i < TILE / 32; i += BLOCK) heads[i] = 0u;
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+      for (int k = 0; k < kScalarHeads; ++k) {
+        const int64_t s = s_lo + k;
+        const int64_t ph = o[k] - shift;
+        if (k < cnt && (REV ? (s >= 1) : (s < a.num_segments)) && ph >= pb && ph < pb + valid) {
+          const int e = REV ? (TILE - 1 - (int)(ph - pb)) : (int)(ph - pb);
+          atomicOr(&heads[e >> 5], 1u << (e & 31));
+        }
+      }
+    }
+    __syncthreads();
+    return waves;
+  }
   for (int i = tid; i < TILE / 32; i += BLOCK) heads[i] = 0u;
   if (tid == 0) *flag = 0u;
   __syncthreads();
-  const int shift = REV ? 1 : 0;
   for (int64_t s = s_lo + tid; s < s_hi; s += BLOCK) {
     const bool real = REV ? (s >= 1) : (s < a.num_segments);
     const int64_t ph = a.offsets[s] - shift;   // physical first element (last for reverse)
     if (real && ph >= pb && ph < pb + valid) {
       const int e = REV ? (TILE - 1 - (int)(ph - pb)) : (int)(ph - pb);
       atomicOr(&heads[e >> 5], 1u << (e & 31));
-      *flag = 1u;
+      atomicOr(flag, 1u << (e / WSPAN));
     }
   }
   __syncthreads();
-  return *flag != 0u;
+  return __builtin_amdgcn_readfirstlane(*flag);
 }
 
 // Buffer resource over one wave's span of WSPAN elements starting at p, of
@@ -406,12 +462,32 @@ __device__ __forceinline__ void load_tile(const KernelArgs &a, int64_t t, int wa
   for (int c = 0; c < SH::CH; ++c) in.load(c, R[c]);
 }
 
-template <class SH, bool NT, bool REV, bool VEC>
-__device__ __forceinline__ void store_tile(const KernelArgs &a, int64_t t, int wave, int lane,
-                                           u32x4 (&R)[SH::CH]) {
-  const WaveSpan<SH, NT, REV, VEC> out(a.out, a, t, wave, lane);
+// One chunk of scan_wave without a segment start: in-lane inclusive
+// partials, the wave scan of the lane totals, then the chunk's prefix within
+// the wave (uniform, wsum; none for the first chunk) joins the lane's
+// offset; inclusive: off + p_k, exclusive: off + p_{k-1}, chosen by selects
+// so every chunk stays in its own registers.  wsum grows by the chunk total.
+template <class Op, bool REV>
+__device__ __forceinline__ void plain_chunk(u32x4 &r, typename Op::carry_t &wsum, bool ex, bool first) {
+  using lane_t = typename Op::lane_t;
+  constexpr int p0 = REV ? 3 : 0, p1 = REV ? 2 : 1, p2 = REV ? 1 : 2, p3 = REV ? 0 : 3;
+  constexpr int ph[4] = {p0, p1, p2, p3};
 #pragma unroll
-  for (int c = 0; c < SH::CH; ++c) out.store(c, R[c]);
+  for (int k = 1; k < 4; ++k) r[ph[k]] = Op::lbits(Op::ladd(Op::lfrom(r[ph[k - 1]]), Op::lfrom(r[ph[k]])));
+  const lane_t x = wave_scan<Op>(Op::lfrom(r[p3]));
+  const lane_t lex = Op::lfrom(lane_up1(Op::lbits(x)));   // lane-exclusive value in the chunk
+  const lane_t ct = Op::lfrom(readlane32(Op::lbits(x), 63));
+  const lane_t off = first ? lex : Op::ladd(Op::narrow(wsum), lex);
+  r[p3] = Op::lbits(Op::ladd(off, Op::lfrom(ex ? r[p2] : r[p3])));
+  r[p2] = Op::lbits(Op::ladd(off, Op::lfrom(ex ? r[p1] : r[p2])));
+  r[p1] = Op::lbits(Op::ladd(off, Op::lfrom(ex ? r[p0] : r[p1])));
+  r[p0] = ex ? Op::lbits(off) : Op::lbits(Op::ladd(off, Op::lfrom(r[p0])));
+  wsum = Op::cadd(wsum, Op::widen(ct));
+  // finish the chunk in its own registers now: without this the compiler
+  // defers the lane-offset add to the final carry add (one three-operand add
+  // per element), keeping one offset register per chunk alive through the
+  // look-back
+  asm volatile("" : "+v"(r));
 }
 
 // In-register scan of this wave's span (the 64-lane form of the horizontal
@@ -420,100 +496,116 @@ __device__ __forceinline__ void store_tile(const KernelArgs &a, int64_t t, int w
 // slot 3-k in reverse tiles, so the values never move between slots and the
 // group is stored back as it was loaded.  On return the slot of logical
 // element k of chunk c holds its wave-local value (inclusive or exclusive,
-// restarted at segment starts), am[c] bit k (segmented) marks the elements
-// the carry into the wave still applies to, and (wsum, wflag) is the wave's
-// total (since its last segment start) and whether it contains a start.
+// restarted at segment starts), fh (segmented, wave-uniform) is the logical
+// position within the wave of its first segment start (WSPAN if none): the
+// carry into the wave applies to the elements before it and to no others;
+// and (wsum, wflag) is the wave's total (since its last segment start) and
+// whether it contains a start.  whead: the wave's span holds a segment start
+// (the bitmap in heads is read only then).  Segmented, the chunks go in
+// groups of Op::kSegGroup: a group without a start takes the plain scan (one
+// uniform branch per group, and the group's chunks still interleave), so
+// segment starts cost only in the groups that hold them.
 template <class Op, class SH, bool SEG, bool REV>
-__device__ __forceinline__ void scan_wave(uint32_t exclusive, int wave, int lane, bool any_head,
-                                          const uint32_t *heads, u32x4 (&R)[SH::CH],
-                                          uint32_t (&am)[SEG ? SH::CH : 1],
+__device__ __forceinline__ void scan_wave(uint32_t exclusive, int wave, int lane, bool whead,
+                                          const uint32_t *heads, u32x4 (&R)[SH::CH], int &fh_out,
                                           typename Op::carry_t &wsum_out, uint32_t &wflag_out) {
   using lane_t = typename Op::lane_t;
   using carry_t = typename Op::carry_t;
   constexpr int p0 = REV ? 3 : 0, p1 = REV ? 2 : 1, p2 = REV ? 1 : 2, p3 = REV ? 0 : 3;
   constexpr int ph[4] = {p0, p1, p2, p3};
+  constexpr int G = SEG ? (Op::kSegGroup < SH::CH ? Op::kSegGroup : SH::CH) : SH::CH;
+  static_assert(SH::CH % G == 0, "chunk groups must tile the wave span");
+  const bool ex = exclusive != 0u;
   carry_t wsum = Op::czero();
   uint32_t wflag = 0u;
-#pragma unroll
-  for (int c = 0; c < SH::CH; ++c) {
-    uint32_t hb = 0u;   // segment starts among this lane's 4 elements (bit k = logical k)
-    if constexpr (SEG) {
-      if (any_head) {
-        const int e0 = wave * SH::WSPAN + c * 256 + lane * 4;
-        hb = (heads[e0 >> 5] >> (e0 & 31)) & 0xfu;
-      }
-    }
+  int fh = SH::WSPAN;
+
+  // Chunk that may hold segment starts (hb: this lane's, bit k = logical k).
+  auto seg_chunk = [&](const int c, const uint32_t hb) {
     // in-lane inclusive partials, restarting at segment starts
 #pragma unroll
     for (int k = 1; k < 4; ++k) {
       const lane_t sum = Op::ladd(Op::lfrom(R[c][ph[k - 1]]), Op::lfrom(R[c][ph[k]]));
-      if constexpr (SEG) R[c][ph[k]] = ((hb >> k) & 1u) ? R[c][ph[k]] : Op::lbits(sum);
-      else R[c][ph[k]] = Op::lbits(sum);
+      R[c][ph[k]] = ((hb >> k) & 1u) ? R[c][ph[k]] : Op::lbits(sum);
     }
     lane_t x = Op::lfrom(R[c][p3]);
     uint32_t f = hb != 0u;
-    uint32_t cf = 0u;
-    if constexpr (SEG) {
-      wave_scan_seg<Op>(x, f);
-      cf = readlane32(f, 63);
-    } else {
-      x = wave_scan<Op>(x);
-    }
-    const lane_t lex = Op::lfrom(lane_up1(Op::lbits(x)));   // lane-exclusive value in the chunk
+    wave_scan_seg<Op>(x, f);
+    const uint32_t cf = readlane32(f, 63);   // the chunk holds a start
+    const lane_t lex = Op::lfrom(lane_up1(Op::lbits(x)));
     const lane_t ct = Op::lfrom(readlane32(Op::lbits(x), 63));
-    // chunk-local values; m marks the elements the carry into the chunk applies to
-    uint32_t m = 0xfu;
-    if constexpr (SEG) {
-      const uint32_t lexf = lane_up1(f);   // a segment starts in an earlier lane of the chunk
-      m = 0u;
-      if (exclusive) {
-        // out_k = head_k ? 0 : value before k in its segment
+    const uint32_t lexf = lane_up1(f);   // a segment starts in an earlier lane of the chunk
+    // m marks the elements before the chunk's first start: the chunk's
+    // prefix within the wave applies to them
+    uint32_t m = 0u;
+    if (ex) {
+      // out_k = head_k ? 0 : value before k in its segment
 #pragma unroll
-        for (int k = 3; k >= 0; --k) {
-          const uint32_t h = (hb >> k) & 1u;
-          const uint32_t before = hb & ((1u << k) - 1u);   // starts strictly before k in the lane
-          const lane_t prev = k ? Op::lfrom(R[c][ph[k ? k - 1 : 0]]) : Op::lzero();
-          const lane_t v = h ? Op::lzero() : (before ? prev : (k ? Op::ladd(lex, prev) : lex));
-          R[c][ph[k]] = Op::lbits(v);
-          m |= (!h && !before && !lexf) ? (1u << k) : 0u;
-        }
-      } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const uint32_t seen = hb & ((2u << k) - 1u);      // starts at or before k
-          if (!seen) R[c][ph[k]] = Op::lbits(Op::ladd(lex, Op::lfrom(R[c][ph[k]])));
-          m |= (!seen && !lexf) ? (1u << k) : 0u;
-        }
+      for (int k = 3; k >= 0; --k) {
+        const uint32_t h = (hb >> k) & 1u;
+        const uint32_t before = hb & ((1u << k) - 1u);   // starts strictly before k in the lane
+        const lane_t prev = k ? Op::lfrom(R[c][ph[k ? k - 1 : 0]]) : Op::lzero();
+        const lane_t v = h ? Op::lzero() : (before ? prev : (k ? Op::ladd(lex, prev) : lex));
+        R[c][ph[k]] = Op::lbits(v);
+        m |= (!h && !before && !lexf) ? (1u << k) : 0u;
       }
     } else {
-      // the chunk's prefix within the wave (uniform) joins the lane's offset;
-      // inclusive: off + p_k, exclusive: off + p_{k-1}, chosen by selects so
-      // every chunk stays in its own registers
-      const lane_t off = c > 0 ? Op::ladd(Op::narrow(wsum), lex) : lex;
-      const bool ex = exclusive != 0u;
-      R[c][p3] = Op::lbits(Op::ladd(off, Op::lfrom(ex ? R[c][p2] : R[c][p3])));
-      R[c][p2] = Op::lbits(Op::ladd(off, Op::lfrom(ex ? R[c][p1] : R[c][p2])));
-      R[c][p1] = Op::lbits(Op::ladd(off, Op::lfrom(ex ? R[c][p0] : R[c][p1])));
-      R[c][p0] = ex ? Op::lbits(off) : Op::lbits(Op::ladd(off, Op::lfrom(R[c][p0])));
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t seen = hb & ((2u << k) - 1u);      // starts at or before k
+        if (!seen) R[c][ph[k]] = Op::lbits(Op::ladd(lex, Op::lfrom(R[c][ph[k]])));
+        m |= (!seen && !lexf) ? (1u << k) : 0u;
+      }
     }
-    // segmented: fold the chunk's prefix within the wave (uniform) into the
-    // elements it applies to
-    if (SEG && c > 0) {
+    if (c > 0) {
       const lane_t cp = Op::narrow(wsum);
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if ((m >> k) & 1u) R[c][ph[k]] = Op::lbits(Op::ladd(cp, Op::lfrom(R[c][ph[k]])));
-      if (wflag) m = 0u;   // a segment started in an earlier chunk of this wave
     }
-    if constexpr (SEG) am[c] = m;
     wsum = cf ? Op::widen(ct) : Op::cadd(wsum, Op::widen(ct));
     wflag |= cf;
-    // finish the chunk in its own registers now: without this the compiler
-    // defers the lane-offset add to the final carry add (one three-operand
-    // add per element), keeping one offset register per chunk alive through
-    // the look-back
     asm volatile("" : "+v"(R[c]));
+  };
+
+  // the lane's bitmap word in chunk 0 and its bit offset there (the same in
+  // every chunk: a chunk is 8 words); the chunk's word index is a constant
+  // offset, so no per-chunk address stays live
+  const uint32_t *hw = heads + ((wave * SH::WSPAN + lane * 4) >> 5);
+  const int hs = (lane * 4) & 31;
+#pragma unroll
+  for (int g = 0; g < SH::CH; g += G) {
+    uint32_t hb[G];
+    uint64_t any = 0ull;
+#pragma unroll
+    for (int j = 0; j < G; ++j) hb[j] = 0u;
+    if constexpr (SEG) {
+      if (whead) {
+        uint32_t o = 0u;
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+          hb[j] = (hw[(g + j) * 8] >> hs) & 0xfu;
+          o |= hb[j];
+        }
+        any = ballot(o != 0u);
+      }
+    }
+    if (!SEG || any == 0ull) {
+#pragma unroll
+      for (int j = 0; j < G; ++j) plain_chunk<Op, REV>(R[g + j], wsum, ex, g + j == 0);
+    } else {
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        const uint64_t hm = ballot(hb[j] != 0u);   // lanes of the chunk with a start
+        if (fh == SH::WSPAN && hm != 0ull) {
+          const int l = __builtin_ctzll(hm);
+          fh = (g + j) * 256 + l * 4 + __builtin_ctz(__builtin_amdgcn_readlane(hb[j], l));
+        }
+        seg_chunk(g + j, hb[j]);
+      }
+    }
   }
+  fh_out = fh;
   wsum_out = wsum;
   wflag_out = wflag;
 }
@@ -564,31 +656,26 @@ __device__ __forceinline__ void publish_first(uint64_t *st, int64_t t, typename 
 }
 
 // Add the carry into the wave's values: R = win + R where the carry applies
-// (every element unless segmented; am[c] bit k is logical element k, in slot
-// 3-k of reverse tiles).
+// (every element unless segmented; segmented, the logical positions before
+// fh, the wave's first segment start; logical element k of a lane's group
+// sits in slot 3-k of reverse tiles).
 template <class Op, class SH, bool SEG, bool REV>
-__device__ __forceinline__ void apply_carry(typename Op::carry_t win, u32x4 (&R)[SH::CH],
-                                            const uint32_t (&am)[SEG ? SH::CH : 1]) {
+__device__ __forceinline__ void apply_carry(typename Op::carry_t win, u32x4 (&R)[SH::CH], int lane, int fh) {
   using lane_t = typename Op::lane_t;
   const lane_t w32 = Op::narrow(win);
+  // element k of chunk c takes the carry when c*256 + k < fh - 4*lane (one
+  // compare against a constant per element, no per-chunk register)
+  const int d = fh - lane * 4;
 #pragma unroll
   for (int c = 0; c < SH::CH; ++c) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int slot = REV ? 3 - k : k;
       const lane_t l = Op::lfrom(R[c][slot]);
-      if constexpr (SEG) R[c][slot] = Op::lbits(((am[c] >> k) & 1u) ? Op::ladd(w32, l) : l);
+      if constexpr (SEG) R[c][slot] = Op::lbits(c * 256 + k < d ? Op::ladd(w32, l) : l);
       else R[c][slot] = Op::lbits(Op::ladd(w32, l));
     }
   }
-}
-
-template <class Op, class SH, bool SEG, bool NT, bool REV, bool VEC>
-__device__ __forceinline__ void finish_tile(const KernelArgs &a, int64_t t, int wave, int lane,
-                                            typename Op::carry_t win, u32x4 (&R)[SH::CH],
-                                            const uint32_t (&am)[SEG ? SH::CH : 1]) {
-  apply_carry<Op, SH, SEG, REV>(win, R, am);
-  store_tile<SH, NT, REV, VEC>(a, t, wave, lane, R);
 }
 
 // End of a workgroup in a static round-robin launch: count it; the last
@@ -697,19 +784,20 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
     if (t >= a.tiles) break;
     if (a.stride && tid == 0) st_agent(a.status + (1 - parity) * a.capacity + t, 0ull);
 
-    bool any_head = false;
-    if constexpr (SEG) any_head = mark_heads<BLOCK, SH::TILE, REV>(a, t, s_heads, &s_flag);
+    uint32_t head_waves = 0u;   // bit w: wave w's span holds a segment start
+    if constexpr (SEG) head_waves = mark_heads<BLOCK, SH::TILE, SH::WSPAN, REV>(a, t, s_heads, &s_flag);
 
     // the tile's loads are in flight: scan in registers, combine the waves
-    uint32_t am[SEG ? SH::CH : 1];
+    int fh;
     carry_t wsum, wpre, agg;
     uint32_t wflag, wpref, aggf;
-    scan_wave<Op, SH, SEG, REV>(a.exclusive, wave, lane, any_head, s_heads, R, am, wsum, wflag);
+    scan_wave<Op, SH, SEG, REV>(a.exclusive, wave, lane, (head_waves >> wave) & 1u, s_heads, R, fh, wsum,
+                                wflag);
     combine_waves<Op, SH::WAVES>(wave, lane, wsum, wflag, s_wtot[slot], s_wflag[slot], wpre, wpref, agg, aggf);
 
     // publish, look back, publish the prefix
     bool first_is_head = false;
-    if constexpr (SEG) first_is_head = any_head && (s_heads[0] & 1u);
+    if constexpr (SEG) first_is_head = (head_waves & 1u) && (s_heads[0] & 1u);
     const bool need_carry = t > 0 && !first_is_head;
     if (multi && wave == 0) {
       uint64_t *st = a.status + parity * a.capacity;
@@ -729,7 +817,10 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
     }
     __syncthreads();
     const carry_t carry = need_carry ? s_carry[slot] : Op::czero();
-    apply_carry<Op, SH, SEG, REV>(wpref ? wpre : Op::cadd(carry, wpre), R, am);
+    const carry_t win = wpref ? wpre : Op::cadd(carry, wpre);
+    // a wave without a segment start may add the carry everywhere (no selects)
+    if (SEG && (!Op::kSplitCarry || fh < SH::WSPAN)) apply_carry<Op, SH, SEG, REV>(win, R, lane, fh);
+    else apply_carry<Op, SH, false, REV>(win, R, lane, fh);
 
     // Store the tile and load the next one into the same registers: the
     // first half of the stores goes out while the next tile is taken from the

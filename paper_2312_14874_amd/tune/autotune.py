@@ -103,8 +103,14 @@ def main():
     p.add_argument("--reps", type=int, default=7)
     p.add_argument("--dtypes", default="int,f32")
     p.add_argument("--segmented", default="0,1")
+    p.add_argument("--merge", action="store_true",
+                   help="keep the entries of --out for the (dtype, segmented) pairs not tuned now")
     args = p.parse_args()
     entries = []
+    tuned = {(d, int(s)) for d in args.dtypes.split(",") for s in args.segmented.split(",")}
+    if args.merge and os.path.exists(args.out):
+        with open(args.out) as f:
+            entries = [e for e in json.load(f)["entries"] if (e["op"], e["segmented"]) not in tuned]
     for dtype in args.dtypes.split(","):
         for seg in [int(s) for s in args.segmented.split(",")]:
             for b in range(args.min, args.max + 1):
@@ -114,6 +120,7 @@ def main():
                                 "block": info["block"], "items": info["items"],
                                 "nontemporal": info["nontemporal"], "mode": info["mode"]})
                 print("best n=2^%d %s seg=%d: config %d" % (b, dtype, seg, best), file=sys.stderr, flush=True)
+    entries.sort(key=lambda e: (e["op"] != "int", e["segmented"], e["log2n"]))
     with open(args.out, "w") as f:
         json.dump({"arch": "gfx950", "format": 1, "entries": entries}, f, indent=1)
     print("wrote", args.out)
