@@ -19,6 +19,10 @@ resident in HBM.  Prints ONE JSON line on stdout; progress goes to stderr.
              [1, 2^20], Poisson(8) int32 counts, exclusive, one persistent
              launch replayed from a hipGraph) against one flat-scan launch per
              segment, eager and graph-captured; all results are compared
+  two_pass   the same n = 2^28 scan by the paper's two-pass algorithms
+             (Section 2.1: Prefix Sum + Increment, Accumulate + Prefix Sum),
+             whole-array and over cache-sized partitions (Section 2.2),
+             against the single pass; results compared with its output
 Extra modes (not the headline line): --n, --dtype f32, --copy-calibration.
 """
 from __future__ import annotations
@@ -77,6 +81,7 @@ def parse():
     p.add_argument("--dtype", choices=["u32", "f32"], default="u32")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     p.add_argument("--no-segmented", action="store_true", help="skip the segmented comparison")
+    p.add_argument("--no-two-pass", action="store_true", help="skip the two-pass comparison")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run only plain device copies of the scan's bytes (counter calibration)")
     return p.parse_args()
@@ -198,6 +203,11 @@ def main():
     if not args.no_segmented and args.dtype == "u32":
         seg = segmented_comparison(scan, torch, np, workloads, oracle, dev)
 
+    # ---------------------------------------------------------- two-pass algorithms vs the single pass
+    two = None
+    if not args.no_two_pass and args.dtype == "u32":
+        two = two_pass_comparison(scan, torch, x, y, kern_ms[K // 2], stream)
+
     del x, y
     traffic = measured_traffic(n) if args.dtype == "u32" else None
     out = {
@@ -223,8 +233,42 @@ def main():
                      "kernel_avg_us": round(kern_avg_ms * 1e3, 2), "algorithmic_bytes": int(alg_bytes)},
         "cpu_baseline": cpu,
         "segmented": seg,
+        "two_pass": two,
     }
     print(json.dumps(out), flush=True)
+
+
+def two_pass_comparison(scan, torch, x, y, single_ms, stream):
+    """The paper's two-pass algorithms on the bench input, whole array and in
+    partitions; each result must equal the single pass's output y."""
+    n = x.numel()
+    z = torch.empty_like(x)
+    rows, equal = [], True
+    for method, floor in (("prefix_increment", 16), ("accumulate_prefix", 12)):
+        for part in (0, 1 << 25, 1 << 24, 1 << 22):
+            def run():
+                scan.two_pass_cumsum(x, method, partition=part, out=z)
+            run()
+            torch.cuda.synchronize()
+            equal = equal and bool(torch.equal(z, y))
+            ts = []
+            for _ in range(10):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                run()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            ts.sort()
+            ms = ts[len(ts) // 2]
+            rows.append({"method": method, "partition": part, "us": round(ms * 1e3, 1),
+                         "GBps_alg": round(8.0 * n / (ms * 1e-3) / 1e9, 1),
+                         "min_bytes_per_elem": floor,
+                         "GBps_min_traffic": round(floor * n / (ms * 1e-3) / 1e9, 1),
+                         "time_vs_single_pass": round(ms / single_ms, 3)})
+            log("two-pass:", rows[-1])
+    return {"workload": "same input as the single pass; 16384-element tiles, one per workgroup; partition 0 = whole array",
+            "single_pass_us": round(single_ms * 1e3, 1), "runs": rows, "results_equal": equal}
 
 
 def segmented_comparison(scan, torch, np, workloads, oracle, dev):

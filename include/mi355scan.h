@@ -98,6 +98,30 @@ scan_status_t scan_segmented_batch(const void *in, void *out, const int64_t *off
                                    int32_t num_segments, int64_t n, scan_dtype_t dtype,
                                    uint32_t flags, hipStream_t stream);
 
+/* ---- two-pass scans (comparison with the single pass) ----
+ * The multithreaded two-pass algorithms of Section 2.1 at device scale, a
+ * workgroup in the role of the paper's thread and a 16384-element tile in the
+ * role of its partition:
+ *  SCAN_TWO_PASS_PREFIX_INCREMENT  ("Prefix Sum + Increment") pass 1 scans
+ *      every tile and writes it, keeping its total; pass 2 adds to every tile
+ *      the sum of the totals before it.  HBM traffic 16 bytes per element.
+ *  SCAN_TWO_PASS_ACCUMULATE_PREFIX ("Accumulate + Prefix Sum") pass 1 only
+ *      adds up every tile; pass 2 scans every tile starting from the sum of
+ *      the totals before it.  HBM traffic 12 bytes per element.
+ * Between the passes one workgroup scans the tile totals.
+ * partition: elements per partition of the cache-friendly scheme of Section
+ * 2.2 (rounded up to whole tiles): both passes run on one partition before
+ * the next starts, so pass 2 may find pass 1's data in the caches; 0 = one
+ * partition holding everything.  Each partition costs three launches.
+ * flags: SCAN_EXCLUSIVE only; SCAN_REVERSE returns SCAN_ERROR_NOT_SUPPORTED.
+ * in == out allowed.  Results: the same contract as scan_flat (bit-exact for
+ * integers, the float32 bound).  Uses the stream's workspace. */
+#define SCAN_TWO_PASS_PREFIX_INCREMENT  0
+#define SCAN_TWO_PASS_ACCUMULATE_PREFIX 1
+scan_status_t scan_two_pass(const void *in, void *out, int64_t n, scan_dtype_t dtype,
+                            uint32_t flags, int32_t method, int64_t partition,
+                            hipStream_t stream);
+
 /* ---- float32 cumsum backward ----
  * For y = inclusive cumsum of x (per segment if offsets != NULL), the
  * gradient is the suffix sum of the upstream gradient:

@@ -87,14 +87,17 @@ struct Workspace {
   uint64_t *pubcnt = nullptr;
   uint64_t *status = nullptr;
   uint32_t *map = nullptr;
+  uint64_t *sums = nullptr;   // two-pass scans: capacity tile totals + one running total
   int64_t capacity = 0;   // tiles
 };
 
 constexpr size_t kStatusOffset = sizeof(WsHeader) + kPubWords * sizeof(uint64_t);
 
-size_t ws_bytes(int64_t cap) {
-  return kStatusOffset + (size_t)cap * 2 * sizeof(uint64_t) + (size_t)(cap + 1) * sizeof(uint32_t);
+size_t map_offset(int64_t cap) { return kStatusOffset + (size_t)cap * 2 * sizeof(uint64_t); }
+size_t sums_offset(int64_t cap) {
+  return (map_offset(cap) + (size_t)(cap + 1) * sizeof(uint32_t) + 7) & ~(size_t)7;
 }
+size_t ws_bytes(int64_t cap) { return sums_offset(cap) + (size_t)(cap + 1) * sizeof(uint64_t); }
 
 scan_status_t ws_alloc(Workspace *w, int device, int64_t cap, hipStream_t stream) {
   const size_t bytes = ws_bytes(cap);
@@ -112,7 +115,8 @@ scan_status_t ws_alloc(Workspace *w, int device, int64_t cap, hipStream_t stream
   w->hdr = reinterpret_cast<WsHeader *>(w->base);
   w->pubcnt = reinterpret_cast<uint64_t *>(w->base + sizeof(WsHeader));
   w->status = reinterpret_cast<uint64_t *>(w->base + kStatusOffset);
-  w->map = reinterpret_cast<uint32_t *>(w->base + kStatusOffset + (size_t)cap * 2 * sizeof(uint64_t));
+  w->map = reinterpret_cast<uint32_t *>(w->base + map_offset(cap));
+  w->sums = reinterpret_cast<uint64_t *>(w->base + sums_offset(cap));
   w->capacity = cap;
   return SCAN_SUCCESS;
 }
@@ -357,6 +361,64 @@ scan_status_t segmented(const void *in, void *out, const int64_t *offsets, int32
   return launch(c, stream, ws, cfg);
 }
 
+// Two-pass scans (Section 2.1), partition by partition (Section 2.2): per
+// partition, pass 1 over its tiles, the scan of their totals (one
+// workgroup, which also carries the running total of the partitions before),
+// pass 2.  All launches go to `stream` in order.
+scan_status_t two_pass(const void *in, void *out, int64_t n, scan_dtype_t dt, uint32_t flags,
+                       int32_t method, int64_t partition, hipStream_t stream) {
+  int r = check_dtype((int)dt);
+  if (r == kOk) r = check_flags(flags);
+  if (r == kOk) r = check_flat(in, out, n);
+  if (r != kOk) return st(r);
+  if (method != SCAN_TWO_PASS_PREFIX_INCREMENT && method != SCAN_TWO_PASS_ACCUMULATE_PREFIX)
+    return SCAN_ERROR_INVALID_VALUE;
+  if (partition < 0) return SCAN_ERROR_INVALID_VALUE;
+  if (flags & SCAN_REVERSE) return SCAN_ERROR_NOT_SUPPORTED;
+  if (n == 0) return SCAN_SUCCESS;
+  ensure_init();
+  int dev = 0;
+  DeviceInfo di;
+  scan_status_t s = current_device(&dev, &di);
+  if (s != SCAN_SUCCESS) return s;
+  const TwoPassKernels &K = kTwoPass;
+  const int64_t tile = (int64_t)K.block * K.items;
+  const int64_t T = tiles_for(n, tile);
+  if (T > kMaxTiles) return SCAN_ERROR_NOT_SUPPORTED;
+  Workspace *ws = nullptr;
+  s = stream_ws(dev, stream, T, &ws);
+  if (s != SCAN_SUCCESS) return s;
+  const int op = opclass_of(dt);
+  const int vec = (((uintptr_t)in | (uintptr_t)out) & 15u) == 0 ? 1 : 0;
+  const int64_t per = partition == 0 ? T : std::max<int64_t>(1, tiles_for(partition, tile));
+  // pass 1 hands its data to pass 2 through the caches only when partitioned
+  const int nt1 = per >= T ? 1 : 0;
+  const bool acc = method == SCAN_TWO_PASS_ACCUMULATE_PREFIX;
+  const void *pass1 = acc ? K.totals[op][vec][nt1] : K.local_scan[op][vec][nt1];
+  const void *pass2 = acc ? K.offset_scan[op][vec] : K.increment[op][vec];
+
+  TwoPassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.k.in = in;
+  a.k.out = out;
+  a.k.n = n;
+  a.k.tiles = T;
+  a.k.exclusive = (flags & SCAN_EXCLUSIVE) ? 1u : 0u;
+  a.sums = ws->sums;
+  a.run = ws->sums + ws->capacity;
+  for (int64_t t0 = 0; t0 < T; t0 += per) {
+    a.tile0 = t0;
+    a.ntiles = std::min<int64_t>(per, T - t0);
+    void *args[] = {&a};
+    hipError_t e = hipLaunchKernel(pass1, dim3((unsigned)a.ntiles), dim3(K.block), args, 0, stream);
+    if (e == hipSuccess)
+      e = hipLaunchKernel(K.scan_totals[op], dim3(1), dim3(K.totals_block), args, 0, stream);
+    if (e == hipSuccess) e = hipLaunchKernel(pass2, dim3((unsigned)a.ntiles), dim3(K.block), args, 0, stream);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return SCAN_SUCCESS;
+}
+
 // Per-segment launches (comparator).  host_offsets are host memory.
 scan_status_t looped(const void *in, void *out, const int64_t *host_offsets, int32_t S,
                      scan_dtype_t dt, uint32_t flags, hipStream_t stream, Workspace *ws) {
@@ -572,6 +634,11 @@ scan_status_t scan_f32_backward(const float *grad_out, float *grad_in, int64_t n
   if (!offsets) return flat(grad_out, grad_in, n, SCAN_F32, SCAN_REVERSE, stream);
   return segmented(grad_out, grad_in, offsets, num_segments, n, SCAN_F32, SCAN_REVERSE, stream,
                    nullptr, -1);
+}
+
+scan_status_t scan_two_pass(const void *in, void *out, int64_t n, scan_dtype_t dtype, uint32_t flags,
+                            int32_t method, int64_t partition, hipStream_t stream) {
+  return two_pass(in, out, n, dtype, flags, method, partition, stream);
 }
 
 scan_status_t scan_reserve(int64_t max_n, hipStream_t stream) {

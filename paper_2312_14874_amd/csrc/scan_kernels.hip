@@ -2,6 +2,7 @@
 // host dispatcher and the autotuner choose from.
 #include "scan_device.hpp"
 #include "scan_table.hpp"
+#include "two_pass.hpp"
 
 namespace mi355scan {
 
@@ -57,5 +58,32 @@ const Config kConfigs[] = {
 const int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
 const void *kTileSegmentMap = (const void *)&tile_segment_map;
+
+// two-pass kernels: 256 threads x 64 elements (16384-element tiles); the
+// trailing template arguments are the kernel's flags, VEC last
+#define MI355SCAN_TP(KERNEL, OP, ...) (const void *)&KERNEL<OP, 256, 64, __VA_ARGS__>
+const TwoPassKernels kTwoPass = {
+    256, 64,
+    {{{MI355SCAN_TP(tile_totals, OpsU32, false, false), MI355SCAN_TP(tile_totals, OpsU32, true, false)},
+      {MI355SCAN_TP(tile_totals, OpsU32, false, true), MI355SCAN_TP(tile_totals, OpsU32, true, true)}},
+     {{MI355SCAN_TP(tile_totals, OpsF32, false, false), MI355SCAN_TP(tile_totals, OpsF32, true, false)},
+      {MI355SCAN_TP(tile_totals, OpsF32, false, true), MI355SCAN_TP(tile_totals, OpsF32, true, true)}}},
+    {{{MI355SCAN_TP(scan_tile_offset, OpsU32, true, false, false),
+       MI355SCAN_TP(scan_tile_offset, OpsU32, true, true, false)},
+      {MI355SCAN_TP(scan_tile_offset, OpsU32, true, false, true),
+       MI355SCAN_TP(scan_tile_offset, OpsU32, true, true, true)}},
+     {{MI355SCAN_TP(scan_tile_offset, OpsF32, true, false, false),
+       MI355SCAN_TP(scan_tile_offset, OpsF32, true, true, false)},
+      {MI355SCAN_TP(scan_tile_offset, OpsF32, true, false, true),
+       MI355SCAN_TP(scan_tile_offset, OpsF32, true, true, true)}}},
+    {{MI355SCAN_TP(scan_tile_offset, OpsU32, false, true, false),
+      MI355SCAN_TP(scan_tile_offset, OpsU32, false, true, true)},
+     {MI355SCAN_TP(scan_tile_offset, OpsF32, false, true, false),
+      MI355SCAN_TP(scan_tile_offset, OpsF32, false, true, true)}},
+    {{MI355SCAN_TP(increment_tiles, OpsU32, true, false), MI355SCAN_TP(increment_tiles, OpsU32, true, true)},
+     {MI355SCAN_TP(increment_tiles, OpsF32, true, false), MI355SCAN_TP(increment_tiles, OpsF32, true, true)}},
+    {(const void *)&scan_totals<OpsU32>, (const void *)&scan_totals<OpsF32>},
+    kTotalsBlock,
+};
 
 }  // namespace mi355scan

@@ -49,6 +49,15 @@ struct KernelArgs {
   uint64_t *pubcnt;           // ordered mode: publish counters [2][kPubSlots], kPubStride words apart
 };
 
+// Arguments of the two-pass kernels (one partition of tiles per launch).
+struct TwoPassArgs {
+  KernelArgs k;      // in, out, n, tiles (of the whole array), exclusive
+  void *sums;        // carry type [tiles]: pass-1 totals, then their exclusive prefixes
+  void *run;         // carry type: sum of the partitions before this one
+  int64_t tile0;     // first tile of this partition
+  int64_t ntiles;    // tiles in this partition
+};
+
 // Ordered launches count published tiles in kPubSlots counters per parity
 // (spread over separate cache lines so their atomics do not serialise on one
 // address); the last tile waits for the count before handing over.

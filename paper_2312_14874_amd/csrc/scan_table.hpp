@@ -32,4 +32,17 @@ extern const Config kConfigs[];
 extern const int kNumConfigs;
 extern const void *kTileSegmentMap;   // the tile -> first segment kernel
 
+// Two-pass kernels (Section 2.1 algorithms, for comparison with the single
+// pass), one tile shape; indices [0 = 32-bit integer, 1 = float32][vec].
+struct TwoPassKernels {
+  int block, items;
+  const void *totals[2][2][2];      // [op][vec][nontemporal]: tile totals (pass 1, Accumulate)
+  const void *local_scan[2][2][2];  // [op][vec][nontemporal]: local scans + totals (pass 1, Prefix Sum)
+  const void *offset_scan[2][2];    // [op][vec]: scans with offset (pass 2, Accumulate + Prefix Sum)
+  const void *increment[2][2];      // [op][vec]: offset adds (pass 2, Prefix Sum + Increment)
+  const void *scan_totals[2];       // [op]: exclusive scan of the tile totals (one workgroup)
+  int totals_block;                 // threads of the scan_totals workgroup
+};
+extern const TwoPassKernels kTwoPass;
+
 }  // namespace mi355scan

@@ -9,8 +9,8 @@ import ctypes
 
 import torch
 
-from ._lib import (SCAN_EXCLUSIVE, SCAN_F32, SCAN_I32, SCAN_REVERSE, SCAN_U32,
-                   check, lib)
+from ._lib import (SCAN_EXCLUSIVE, SCAN_F32, SCAN_I32, SCAN_REVERSE, SCAN_TWO_PASS_ACCUMULATE_PREFIX,
+                   SCAN_TWO_PASS_PREFIX_INCREMENT, SCAN_U32, check, lib)
 
 _DTYPES = {torch.int32: SCAN_I32, torch.float32: SCAN_F32}
 if hasattr(torch, "uint32"):
@@ -95,6 +95,27 @@ def segmented_scan_looped(x: torch.Tensor, host_offsets, exclusive: bool = False
         check(lib.scan_segmented_looped(x.data_ptr(), out.data_ptr(), off.ctypes.data, off.size - 1,
                                         dt, _flags(exclusive, reverse), _stream(x.device)),
               "scan_segmented_looped")
+    return out
+
+
+TWO_PASS_METHODS = {"prefix_increment": SCAN_TWO_PASS_PREFIX_INCREMENT,
+                    "accumulate_prefix": SCAN_TWO_PASS_ACCUMULATE_PREFIX}
+
+
+def two_pass_cumsum(x: torch.Tensor, method: str = "accumulate_prefix", exclusive: bool = False,
+                    partition: int = 0, out=None) -> torch.Tensor:
+    """Comparison path: the same scan by one of the paper's two-pass algorithms
+    ("prefix_increment": scan then add offsets, 16 B/element of HBM traffic;
+    "accumulate_prefix": sum then scan with offsets, 12 B/element), over
+    partitions of `partition` elements (0 = one partition)."""
+    if method not in TWO_PASS_METHODS:
+        raise ValueError("method must be one of %s" % sorted(TWO_PASS_METHODS))
+    dt = _check_tensor(x, "x")
+    out = _out_like(x, out)
+    with torch.cuda.device(x.device):
+        check(lib.scan_two_pass(x.data_ptr(), out.data_ptr(), x.numel(), dt, _flags(exclusive, False),
+                                TWO_PASS_METHODS[method], int(partition), _stream(x.device)),
+              "scan_two_pass")
     return out
 
 

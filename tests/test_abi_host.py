@@ -72,6 +72,18 @@ def test_segmented_argument_errors():
     assert f(4096, 4100, 16, 3, 10, 0, 0, None) == OVERLAP
 
 
+def test_two_pass_argument_errors():
+    L = _lib()
+    f = L.lib.scan_two_pass
+    assert f(None, None, 0, 0, 0, 0, 0, None) == 0                  # n = 0: no-op
+    assert f(None, None, 10, 0, 0, 0, 0, None) == INVALID           # null pointers
+    assert f(4096, 8192, 10, 0, 0, 2, 0, None) == INVALID           # unknown method
+    assert f(4096, 8192, 10, 0, 0, 1, -1, None) == INVALID          # partition < 0
+    assert f(4096, 8192, 10, 3, 0, 1, 0, None) == INVALID           # unknown dtype
+    assert f(4096, 4100, 10, 0, 0, 1, 0, None) == OVERLAP
+    assert f(4096, 8192, 10, 0, 2, 1, 0, None) == 5                 # reverse: not supported
+
+
 def test_other_argument_errors():
     L = _lib()
     assert L.lib.scan_reserve(-1, None) == INVALID
