@@ -23,6 +23,8 @@ resident in HBM.  Prints ONE JSON line on stdout; progress goes to stderr.
              (Section 2.1: Prefix Sum + Increment, Accumulate + Prefix Sum),
              whole-array and over cache-sized partitions (Section 2.2),
              against the single pass; results compared with its output
+  operators  the same input scanned with max, min and xor (int32), kernel
+             time from HIP events, each result checked against the oracle
 Extra modes (not the headline line): --n, --dtype f32, --copy-calibration.
 """
 from __future__ import annotations
@@ -82,6 +84,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     p.add_argument("--no-segmented", action="store_true", help="skip the segmented comparison")
     p.add_argument("--no-two-pass", action="store_true", help="skip the two-pass comparison")
+    p.add_argument("--no-operators", action="store_true", help="skip the max / min / xor scans")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run only plain device copies of the scan's bytes (counter calibration)")
     return p.parse_args()
@@ -208,6 +211,11 @@ def main():
     if not args.no_two_pass and args.dtype == "u32":
         two = two_pass_comparison(scan, torch, x, y, kern_ms[K // 2], stream)
 
+    # ---------------------------------------------------------- other operators on the same input
+    ops = None
+    if not args.no_operators and args.dtype == "u32":
+        ops = operator_runs(scan, torch, np, oracle, a, x, y, stream)
+
     del x, y
     traffic = measured_traffic(n) if args.dtype == "u32" else None
     out = {
@@ -234,8 +242,37 @@ def main():
         "cpu_baseline": cpu,
         "segmented": seg,
         "two_pass": two,
+        "operators": ops,
     }
     print(json.dumps(out), flush=True)
+
+
+def operator_runs(scan, torch, np, oracle, a, x, y, stream):
+    """max / min / xor inclusive scans of the bench input read as int32."""
+    n = x.numel()
+    res = {"workload": "inclusive scan of the same n=2^%d input read as int32 (signed compares)" % (n.bit_length() - 1)}
+    ok = True
+    for op in ("max", "min", "xor"):
+        def run():
+            scan.cumsum(x, op=op, out=y)
+        run()
+        torch.cuda.synchronize()
+        ok = ok and np.array_equal(y.cpu().numpy(), oracle.scan_op(a.view(np.int32), op))
+        ts = []
+        for _ in range(20):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            run()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ts.sort()
+        ms = ts[len(ts) // 2]
+        res[op + "_us"] = round(ms * 1e3, 1)
+        res[op + "_GBps"] = round(8.0 * n / (ms * 1e-3) / 1e9, 1)
+        log("operator %s: %.1f us" % (op, ms * 1e3))
+    res["results_equal_oracle"] = bool(ok)
+    return res
 
 
 def two_pass_comparison(scan, torch, x, y, single_ms, stream):

@@ -70,6 +70,20 @@ typedef enum { SCAN_I32 = 0, SCAN_U32 = 1, SCAN_F32 = 2 } scan_dtype_t;
 /* Flag bits. */
 #define SCAN_EXCLUSIVE 0x1u  /* exclusive scan (identity first)              */
 #define SCAN_REVERSE   0x2u  /* suffix scan: out[i] = a[i] + ... + a[n-1]     */
+/* Operator field (bits 2-3).  The Introduction defines the scan for any
+ * associative operator with an identity; besides + (the default, field 0)
+ * the integer dtypes take:
+ *   SCAN_OP_MAX  maximum  (identity INT32_MIN for i32, 0 for u32)
+ *   SCAN_OP_MIN  minimum  (identity INT32_MAX for i32, UINT32_MAX for u32)
+ *   SCAN_OP_XOR  bitwise exclusive or (identity 0)
+ * i32 compares as signed, u32 as unsigned; the exclusive first element is
+ * the identity.  Valid for flat, segmented, looped and graph calls; float32
+ * with an operator other than +, SCAN_REVERSE with SCAN_OP_MIN, and
+ * SCAN_REVERSE with SCAN_OP_MAX on i32 return SCAN_ERROR_NOT_SUPPORTED, and so
+ * do the two-pass scans with any operator other than +. */
+#define SCAN_OP_MAX    0x4u
+#define SCAN_OP_MIN    0x8u
+#define SCAN_OP_XOR    0xCu
 
 /* ---- flat scans (Introduction: definition; Section 2: in place or not) ----
  * in, out: device arrays of n elements (in == out allowed).  n >= 0. */
@@ -80,7 +94,8 @@ scan_status_t scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, hip
 scan_status_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t stream);
 scan_status_t scan_exclusive_f32(const float *in, float *out, int64_t n, hipStream_t stream);
 
-/* General flat scan: any dtype, flags = SCAN_EXCLUSIVE | SCAN_REVERSE. */
+/* General flat scan: any dtype, flags = SCAN_EXCLUSIVE | SCAN_REVERSE, plus
+ * an operator (SCAN_OP_*) for i32 / u32. */
 scan_status_t scan_flat(const void *in, void *out, int64_t n, scan_dtype_t dtype,
                         uint32_t flags, hipStream_t stream);
 

@@ -52,8 +52,11 @@ def _load():
         lib.oracle_scan_f32_f64.argtypes = [P, P, P, I64, I, I]
         lib.oracle_segmented_u32.argtypes = [P, P, P, I64, I, I]
         lib.oracle_segmented_f32_f64.argtypes = [P, P, P, P, I64, I, I]
+        lib.oracle_scan_op_u32.argtypes = [P, P, I64, I, I, I, I]
+        lib.oracle_segmented_op_u32.argtypes = [P, P, P, I64, I, I, I, I]
         for f in (lib.oracle_scan_u32, lib.oracle_scan_f32_f64,
-                  lib.oracle_segmented_u32, lib.oracle_segmented_f32_f64):
+                  lib.oracle_segmented_u32, lib.oracle_segmented_f32_f64,
+                  lib.oracle_scan_op_u32, lib.oracle_segmented_op_u32):
             f.restype = None
         _lib = lib
     return _lib
@@ -128,6 +131,31 @@ def segmented_f32(a: np.ndarray, offsets: np.ndarray, exclusive: bool = False,
     _load().oracle_segmented_f32_f64(_ptr(src), _ptr(s), _ptr(ab), _ptr(off),
                                      off.size - 1, int(exclusive), int(reverse))
     return s, ab
+
+
+OPERATORS = {"max": 1, "min": 2, "xor": 3}
+
+
+def scan_op(a: np.ndarray, op: str, exclusive: bool = False, reverse: bool = False) -> np.ndarray:
+    """Scan of 32-bit integers with another associative operator of the
+    Introduction's definition: "max", "min" (signed for int32, unsigned for
+    uint32) or "xor"; the exclusive form starts from the operator's identity."""
+    src = _as_u32(a)
+    dst = np.empty_like(src)
+    _load().oracle_scan_op_u32(_ptr(src), _ptr(dst), src.size, OPERATORS[op],
+                               int(np.asarray(a).dtype == np.int32), int(exclusive), int(reverse))
+    return dst.view(np.asarray(a).dtype)
+
+
+def segmented_op(a: np.ndarray, offsets: np.ndarray, op: str, exclusive: bool = False,
+                 reverse: bool = False) -> np.ndarray:
+    """Per-segment scan_op (restart from the identity at every segment start)."""
+    src = _as_u32(a)
+    off = _check_offsets(offsets, src.size)
+    dst = np.empty_like(src)
+    _load().oracle_segmented_op_u32(_ptr(src), _ptr(dst), _ptr(off), off.size - 1, OPERATORS[op],
+                                    int(np.asarray(a).dtype == np.int32), int(exclusive), int(reverse))
+    return dst.view(np.asarray(a).dtype)
 
 
 def f32_tolerance(abs_sums: np.ndarray) -> np.ndarray:

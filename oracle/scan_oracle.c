@@ -38,6 +38,60 @@
 #include <stdint.h>
 #include <math.h>
 
+/* ---- other operators ---------------------------------------------------
+ * The Introduction defines the scan for any associative operator with an
+ * identity.  Besides +, the oracle computes three on 32-bit integers, by the
+ * same sequential pass starting from the identity:
+ *   op 1 max, op 2 min (signed when is_signed != 0, else unsigned), op 3 xor.
+ * Identities: max INT32_MIN / 0, min INT32_MAX / UINT32_MAX, xor 0.  The
+ * exclusive form writes the identity first.  */
+static uint32_t op_identity(int op, int is_signed)
+{
+    switch (op) {
+    case 1: return is_signed ? 0x80000000u : 0u;
+    case 2: return is_signed ? 0x7FFFFFFFu : 0xFFFFFFFFu;
+    default: return 0u;
+    }
+}
+
+static uint32_t op_apply(int op, int is_signed, uint32_t acc, uint32_t x)
+{
+    switch (op) {
+    case 1:
+        if (is_signed) return (int32_t)x > (int32_t)acc ? x : acc;
+        return x > acc ? x : acc;
+    case 2:
+        if (is_signed) return (int32_t)x < (int32_t)acc ? x : acc;
+        return x < acc ? x : acc;
+    default:
+        return acc ^ x;
+    }
+}
+
+void oracle_scan_op_u32(const uint32_t *a, uint32_t *out, int64_t n, int op,
+                        int is_signed, int exclusive, int reverse)
+{
+    uint32_t acc = op_identity(op, is_signed);
+    int64_t i = reverse ? n - 1 : 0;
+    int64_t step = reverse ? -1 : 1;
+    for (int64_t k = 0; k < n; ++k, i += step) {
+        uint32_t x = a[i];
+        if (exclusive) { out[i] = acc; acc = op_apply(op, is_signed, acc, x); }
+        else           { acc = op_apply(op, is_signed, acc, x); out[i] = acc; }
+    }
+}
+
+void oracle_segmented_op_u32(const uint32_t *a, uint32_t *out,
+                             const int64_t *offsets, int64_t num_segments,
+                             int op, int is_signed, int exclusive, int reverse)
+{
+    for (int64_t s = 0; s < num_segments; ++s) {
+        int64_t lo = offsets[s], hi = offsets[s + 1];
+        if (hi > lo)
+            oracle_scan_op_u32(a + lo, out + lo, hi - lo, op, is_signed, exclusive, reverse);
+    }
+}
+
 /* ---- flat scans -------------------------------------------------------- */
 
 void oracle_scan_u32(const uint32_t *a, uint32_t *out, int64_t n,

@@ -213,12 +213,22 @@ struct Call {
   const void *in;
   void *out;
   int64_t n;
-  int opclass;
+  int opclass;   // tuning class: 0 = 32-bit integer, 1 = float32
   bool seg;
   uint32_t flags;
   const int64_t *offsets;
   int64_t num_segments;
+  int kind = 0;        // kernel kind (operator), see kernel_kind
+  uint32_t key = 0u;   // keyed max: x ^ key
 };
+
+Call make_call(const void *in, void *out, int64_t n, scan_dtype_t dt, bool seg, uint32_t flags,
+               const int64_t *offsets, int64_t num_segments) {
+  Call c{in, out, n, opclass_of(dt), seg, flags, offsets, num_segments};
+  c.kind = kernel_kind((int)dt, flags);
+  c.key = op_key((int)dt, flags);
+  return c;
+}
 
 bool call_aligned(const Call &c) {
   return ((uintptr_t)c.in & 15u) == 0 && ((uintptr_t)c.out & 15u) == 0;
@@ -258,7 +268,7 @@ scan_status_t launch(const Call &c, hipStream_t stream, Workspace *ws_override, 
   const int64_t T = tiles_for(c.n, tile);
   if (T > kMaxTiles) return SCAN_ERROR_NOT_SUPPORTED;
   const int per_cu = call_per_cu(c, cfg);
-  const void *fn = sh.fn[c.opclass][c.seg ? 1 : 0][(c.flags & SCAN_REVERSE) ? 1 : 0];
+  const void *fn = sh.fn[c.kind][c.seg ? 1 : 0][(c.flags & SCAN_REVERSE) ? 1 : 0];
   const int cu_pct = call_cu_pct(c, cfg);
 
   Workspace *ws = nullptr;
@@ -290,6 +300,7 @@ scan_status_t launch(const Call &c, hipStream_t stream, Workspace *ws_override, 
   }
   a.exclusive = (c.flags & SCAN_EXCLUSIVE) ? 1u : 0u;
   a.reverse = (c.flags & SCAN_REVERSE) ? 1u : 0u;
+  a.key = c.key;
 
   const int threads = sh.block;
   int64_t grid = T;
@@ -342,10 +353,11 @@ scan_status_t flat(const void *in, void *out, int64_t n, scan_dtype_t dt, uint32
   int r = check_dtype((int)dt);
   if (r == kOk) r = check_flags(flags);
   if (r == kOk) r = check_flat(in, out, n);
+  if (r == kOk) r = check_operator((int)dt, flags);
   if (r != kOk) return st(r);
   if (n == 0) return SCAN_SUCCESS;
   ensure_init();
-  Call c{in, out, n, opclass_of(dt), false, flags, nullptr, 0};
+  Call c = make_call(in, out, n, dt, false, flags, nullptr, 0);
   return launch(c, stream, nullptr, -1);
 }
 
@@ -354,10 +366,11 @@ scan_status_t segmented(const void *in, void *out, const int64_t *offsets, int32
   int r = check_dtype((int)dt);
   if (r == kOk) r = check_flags(flags);
   if (r == kOk) r = check_segmented(in, out, offsets, S, n);
+  if (r == kOk) r = check_operator((int)dt, flags);
   if (r != kOk) return st(r);
   if (n == 0) return SCAN_SUCCESS;
   ensure_init();
-  Call c{in, out, n, opclass_of(dt), true, flags, offsets, S};
+  Call c = make_call(in, out, n, dt, true, flags, offsets, S);
   return launch(c, stream, ws, cfg);
 }
 
@@ -371,6 +384,7 @@ scan_status_t two_pass(const void *in, void *out, int64_t n, scan_dtype_t dt, ui
   if (r == kOk) r = check_flags(flags);
   if (r == kOk) r = check_flat(in, out, n);
   if (r != kOk) return st(r);
+  if (op_of(flags) != kOpSum) return SCAN_ERROR_NOT_SUPPORTED;
   if (method != SCAN_TWO_PASS_PREFIX_INCREMENT && method != SCAN_TWO_PASS_ACCUMULATE_PREFIX)
     return SCAN_ERROR_INVALID_VALUE;
   if (partition < 0) return SCAN_ERROR_INVALID_VALUE;
@@ -424,6 +438,7 @@ scan_status_t looped(const void *in, void *out, const int64_t *host_offsets, int
                      scan_dtype_t dt, uint32_t flags, hipStream_t stream, Workspace *ws) {
   int r = check_dtype((int)dt);
   if (r == kOk) r = check_flags(flags);
+  if (r == kOk) r = check_operator((int)dt, flags);
   if (r != kOk) return st(r);
   if (S < 0 || (S > 0 && !host_offsets)) return SCAN_ERROR_INVALID_VALUE;
   if (S == 0) return SCAN_SUCCESS;
@@ -439,7 +454,7 @@ scan_status_t looped(const void *in, void *out, const int64_t *host_offsets, int
   for (int32_t s = 0; s < S; ++s) {
     const int64_t lo = host_offsets[s], len = host_offsets[s + 1] - lo;
     if (len == 0) continue;
-    Call c{pi + 4 * lo, po + 4 * lo, len, opclass_of(dt), false, flags, nullptr, 0};
+    Call c = make_call(pi + 4 * lo, po + 4 * lo, len, dt, false, flags, nullptr, 0);
     scan_status_t e = launch(c, stream, ws, -1);
     if (e != SCAN_SUCCESS) return e;
   }
@@ -673,10 +688,11 @@ scan_status_t scan_segmented_graph_create(const void *in, void *out, const int64
   int r = check_dtype((int)dtype);
   if (r == kOk) r = check_flags(flags);
   if (r == kOk) r = check_segmented(in, out, offsets, num_segments, n);
+  if (r == kOk) r = check_operator((int)dtype, flags);
   if (r != kOk) return st(r);
   ensure_init();
   const int cfg = select_config(opclass_of(dtype), true, n);
-  Call c{in, out, n, opclass_of(dtype), true, flags, offsets, num_segments};
+  Call c = make_call(in, out, n, dtype, true, flags, offsets, num_segments);
   const int64_t need = call_tiles(c, cfg);
   return capture(need, stream,
                  [&](hipStream_t cs, Workspace *ws) {
@@ -694,7 +710,7 @@ scan_status_t scan_looped_graph_create(const void *in, void *out, const int64_t 
   for (int32_t s = 0; s < num_segments; ++s) {
     const int64_t len = host_offsets[s + 1] - host_offsets[s];
     if (len > 0) {
-      Call c{in, out, len, opclass_of(dtype), false, flags, nullptr, 0};
+      Call c = make_call(in, out, len, dtype, false, flags, nullptr, 0);
       need = std::max(need, call_tiles(c, select_config(c.opclass, false, len)));
     }
   }
@@ -765,6 +781,7 @@ scan_status_t scan_autotune(const void *in, void *out, int64_t n, const int64_t 
   if (r == kOk) r = check_flags(flags);
   const bool seg = offsets != nullptr;
   if (r == kOk) r = seg ? check_segmented(in, out, offsets, num_segments, n) : check_flat(in, out, n);
+  if (r == kOk) r = check_operator((int)dtype, flags);
   if (r != kOk) return st(r);
   if (n == 0 || reps < 1) return SCAN_ERROR_INVALID_VALUE;
   ensure_init();
@@ -776,7 +793,7 @@ scan_status_t scan_autotune(const void *in, void *out, int64_t n, const int64_t 
     (void)hipEventDestroy(e0);
     return hip_fail(e);
   }
-  Call c{in, out, n, opclass_of(dtype), seg, flags, offsets, num_segments};
+  Call c = make_call(in, out, n, dtype, seg, flags, offsets, num_segments);
   float best_ms = 1e30f;
   int best_cfg = -1;
   scan_status_t s = SCAN_SUCCESS;

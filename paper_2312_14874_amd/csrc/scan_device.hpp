@@ -33,6 +33,8 @@ struct OpsU32 {
   using lane_t = uint32_t;    // per-lane arithmetic (up to 256-element chunks)
   using carry_t = uint32_t;   // chunk, wave, tile and inter-tile arithmetic
   static constexpr bool kExact = true;
+  // the operator works on keyed values x ^ key (see OpsMaxU32)
+  static constexpr bool kKeyed = false;
   // segmented scans: chunks per plain/segmented branch group, and whether a
   // wave without a segment start takes a separate select-free carry add
   // (both chosen by measurement; the float64 carries of OpsF32 need more
@@ -64,6 +66,7 @@ struct OpsF32 {
   using lane_t = float;
   using carry_t = double;
   static constexpr bool kExact = false;
+  static constexpr bool kKeyed = false;
   static constexpr int kSegGroup = 2;
   static constexpr bool kSplitCarry = false;
   __device__ static lane_t lzero() { return 0.0f; }
@@ -80,6 +83,26 @@ struct OpsF32 {
   __device__ static uint32_t flag_of(uint64_t w) { return (uint32_t)(w & 3u); }
   __device__ static carry_t value_of(uint64_t w) { return __builtin_bit_cast(double, w & ~3ull); }
   __device__ static carry_t canon(carry_t x) { return value_of(pack(x, 0)); }
+};
+
+// Other associative operators of the Introduction's definition, on 32-bit
+// integers (everything else as OpsU32: the identity of each is 0 in the form
+// the kernel computes on, so lanes shifted in by DPP, the exclusive first
+// element and a tile's empty carry need nothing new).
+//   max / min: one unsigned max over keyed values k(x) = x ^ key, an order
+//   isomorphism (or anti-isomorphism) onto uint32 that sends the operator's
+//   identity to 0: key 0 = unsigned max, 0x80000000 = signed max (INT_MIN ->
+//   0), 0xFFFFFFFF = unsigned min (complement), 0x7FFFFFFF = signed min.
+//   The key is applied to a chunk before its scan and removed after the carry.
+struct OpsMaxU32 : OpsU32 {
+  static constexpr bool kKeyed = true;
+  __device__ static lane_t ladd(lane_t a, lane_t b) { return a > b ? a : b; }
+  __device__ static carry_t cadd(carry_t a, carry_t b) { return a > b ? a : b; }
+};
+//   xor: bitwise exclusive or (identity 0).
+struct OpsXorU32 : OpsU32 {
+  __device__ static lane_t ladd(lane_t a, lane_t b) { return a ^ b; }
+  __device__ static carry_t cadd(carry_t a, carry_t b) { return a ^ b; }
 };
 
 // ------------------------------------------------------------ memory helpers
@@ -468,10 +491,12 @@ __device__ __forceinline__ void load_tile(const KernelArgs &a, int64_t t, int wa
 // offset; inclusive: off + p_k, exclusive: off + p_{k-1}, chosen by selects
 // so every chunk stays in its own registers.  wsum grows by the chunk total.
 template <class Op, bool REV>
-__device__ __forceinline__ void plain_chunk(u32x4 &r, typename Op::carry_t &wsum, bool ex, bool first) {
+__device__ __forceinline__ void plain_chunk(u32x4 &r, typename Op::carry_t &wsum, bool ex, bool first,
+                                            uint32_t key) {
   using lane_t = typename Op::lane_t;
   constexpr int p0 = REV ? 3 : 0, p1 = REV ? 2 : 1, p2 = REV ? 1 : 2, p3 = REV ? 0 : 3;
   constexpr int ph[4] = {p0, p1, p2, p3};
+  if constexpr (Op::kKeyed) r ^= key;
 #pragma unroll
   for (int k = 1; k < 4; ++k) r[ph[k]] = Op::lbits(Op::ladd(Op::lfrom(r[ph[k - 1]]), Op::lfrom(r[ph[k]])));
   const lane_t x = wave_scan<Op>(Op::lfrom(r[p3]));
@@ -506,7 +531,7 @@ __device__ __forceinline__ void plain_chunk(u32x4 &r, typename Op::carry_t &wsum
 // uniform branch per group, and the group's chunks still interleave), so
 // segment starts cost only in the groups that hold them.
 template <class Op, class SH, bool SEG, bool REV>
-__device__ __forceinline__ void scan_wave(uint32_t exclusive, int wave, int lane, bool whead,
+__device__ __forceinline__ void scan_wave(uint32_t exclusive, uint32_t key, int wave, int lane, bool whead,
                                           const uint32_t *heads, u32x4 (&R)[SH::CH], int &fh_out,
                                           typename Op::carry_t &wsum_out, uint32_t &wflag_out) {
   using lane_t = typename Op::lane_t;
@@ -522,6 +547,7 @@ __device__ __forceinline__ void scan_wave(uint32_t exclusive, int wave, int lane
 
   // Chunk that may hold segment starts (hb: this lane's, bit k = logical k).
   auto seg_chunk = [&](const int c, const uint32_t hb) {
+    if constexpr (Op::kKeyed) R[c] ^= key;
     // in-lane inclusive partials, restarting at segment starts
 #pragma unroll
     for (int k = 1; k < 4; ++k) {
@@ -592,7 +618,7 @@ __device__ __forceinline__ void scan_wave(uint32_t exclusive, int wave, int lane
     }
     if (!SEG || any == 0ull) {
 #pragma unroll
-      for (int j = 0; j < G; ++j) plain_chunk<Op, REV>(R[g + j], wsum, ex, g + j == 0);
+      for (int j = 0; j < G; ++j) plain_chunk<Op, REV>(R[g + j], wsum, ex, g + j == 0, key);
     } else {
 #pragma unroll
       for (int j = 0; j < G; ++j) {
@@ -660,7 +686,8 @@ __device__ __forceinline__ void publish_first(uint64_t *st, int64_t t, typename 
 // fh, the wave's first segment start; logical element k of a lane's group
 // sits in slot 3-k of reverse tiles).
 template <class Op, class SH, bool SEG, bool REV>
-__device__ __forceinline__ void apply_carry(typename Op::carry_t win, u32x4 (&R)[SH::CH], int lane, int fh) {
+__device__ __forceinline__ void apply_carry(typename Op::carry_t win, u32x4 (&R)[SH::CH], int lane, int fh,
+                                            uint32_t key = 0u) {
   using lane_t = typename Op::lane_t;
   const lane_t w32 = Op::narrow(win);
   // element k of chunk c takes the carry when c*256 + k < fh - 4*lane (one
@@ -675,6 +702,7 @@ __device__ __forceinline__ void apply_carry(typename Op::carry_t win, u32x4 (&R)
       if constexpr (SEG) R[c][slot] = Op::lbits(c * 256 + k < d ? Op::ladd(w32, l) : l);
       else R[c][slot] = Op::lbits(Op::ladd(w32, l));
     }
+    if constexpr (Op::kKeyed) R[c] ^= key;   // back from the keyed form
   }
 }
 
@@ -791,8 +819,8 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
     int fh;
     carry_t wsum, wpre, agg;
     uint32_t wflag, wpref, aggf;
-    scan_wave<Op, SH, SEG, REV>(a.exclusive, wave, lane, (head_waves >> wave) & 1u, s_heads, R, fh, wsum,
-                                wflag);
+    scan_wave<Op, SH, SEG, REV>(a.exclusive, a.key, wave, lane, (head_waves >> wave) & 1u, s_heads, R, fh,
+                                wsum, wflag);
     combine_waves<Op, SH::WAVES>(wave, lane, wsum, wflag, s_wtot[slot], s_wflag[slot], wpre, wpref, agg, aggf);
 
     // publish, look back, publish the prefix
@@ -819,8 +847,8 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
     const carry_t carry = need_carry ? s_carry[slot] : Op::czero();
     const carry_t win = wpref ? wpre : Op::cadd(carry, wpre);
     // a wave without a segment start may add the carry everywhere (no selects)
-    if (SEG && (!Op::kSplitCarry || fh < SH::WSPAN)) apply_carry<Op, SH, SEG, REV>(win, R, lane, fh);
-    else apply_carry<Op, SH, false, REV>(win, R, lane, fh);
+    if (SEG && (!Op::kSplitCarry || fh < SH::WSPAN)) apply_carry<Op, SH, SEG, REV>(win, R, lane, fh, a.key);
+    else apply_carry<Op, SH, false, REV>(win, R, lane, fh, a.key);
 
     // Store the tile and load the next one into the same registers: the
     // first half of the stores goes out while the next tile is taken from the

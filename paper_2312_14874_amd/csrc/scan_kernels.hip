@@ -6,6 +6,9 @@
 
 namespace mi355scan {
 
+// fn[kind][seg][rev], kind: 0 = 32-bit integer sum, 1 = float32 sum, 2 = max /
+// min (keyed unsigned max), 3 = xor; the integer operators share the integer
+// sum's register targets.
 // W[op][seg]: waves per SIMD the register allocation targets (per shape,
 // the most at which the flat variants do not spill).  Workgroups of 768 and
 // 1024 threads need 3 and 4 waves per SIMD to fit at all; some of their
@@ -18,7 +21,15 @@ namespace mi355scan {
    {{(const void *)&scan_tiles<OpsF32, B, I, false, (NT != 0), false, VEC, WFF>,               \
      (const void *)&scan_tiles<OpsF32, B, I, false, (NT != 0), true, VEC, WFF>},               \
     {(const void *)&scan_tiles<OpsF32, B, I, true, (NT != 0), false, VEC, WFS>,                \
-     (const void *)&scan_tiles<OpsF32, B, I, true, (NT != 0), true, VEC, WFS>}}}
+     (const void *)&scan_tiles<OpsF32, B, I, true, (NT != 0), true, VEC, WFS>}},               \
+   {{(const void *)&scan_tiles<OpsMaxU32, B, I, false, (NT != 0), false, VEC, WUF>,            \
+     (const void *)&scan_tiles<OpsMaxU32, B, I, false, (NT != 0), true, VEC, WUF>},            \
+    {(const void *)&scan_tiles<OpsMaxU32, B, I, true, (NT != 0), false, VEC, WUS>,             \
+     (const void *)&scan_tiles<OpsMaxU32, B, I, true, (NT != 0), true, VEC, WUS>}},            \
+   {{(const void *)&scan_tiles<OpsXorU32, B, I, false, (NT != 0), false, VEC, WUF>,            \
+     (const void *)&scan_tiles<OpsXorU32, B, I, false, (NT != 0), true, VEC, WUF>},            \
+    {(const void *)&scan_tiles<OpsXorU32, B, I, true, (NT != 0), false, VEC, WUS>,             \
+     (const void *)&scan_tiles<OpsXorU32, B, I, true, (NT != 0), true, VEC, WUS>}}}
 
 // {block, items, nontemporal, waves per SIMD: u32 flat, f32 flat, u32 segmented, f32 segmented}
 #define MI355SCAN_TILES(B, I, NT, WUF, WFF, WUS, WFS) \

@@ -47,6 +47,7 @@ struct KernelArgs {
   uint32_t ordered;           // tile = blockIdx.x (no counter; relies on in-order dispatch)
   uint32_t stride;            // static round robin: workgroup b takes tiles b, b+stride, ... (co-resident grid)
   uint64_t *pubcnt;           // ordered mode: publish counters [2][kPubSlots], kPubStride words apart
+  uint32_t key;               // keyed operators (max / min): values are scanned as x ^ key
 };
 
 // Arguments of the two-pass kernels (one partition of tiles per launch).

@@ -8,7 +8,9 @@ struct KernelShape {
   int block;         // threads per workgroup
   int items;         // elements per thread (multiple of 4); the tile is block * items
   int nontemporal;   // non-temporal load/store hints
-  const void *fn[2][2][2];   // [0 = 32-bit integer, 1 = float32][segmented][reverse]
+  // [kind: 0 = 32-bit integer sum, 1 = float32 sum, 2 = integer max / min
+  //  (keyed), 3 = integer xor][segmented][reverse]
+  const void *fn[4][2][2];
 };
 
 enum TileMode {

@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(BLOCK) scan_tile_offset(TwoPassArgs a) {
   int fh;
   carry_t wsum, wpre, agg;
   uint32_t wflag, wpref, aggf;
-  scan_wave<Op, SH, false, false>(a.k.exclusive, wave, lane, false, nullptr, R, fh, wsum, wflag);
+  scan_wave<Op, SH, false, false>(a.k.exclusive, 0u, wave, lane, false, nullptr, R, fh, wsum, wflag);
   combine_waves<Op, SH::WAVES>(wave, lane, wsum, wflag, s_wtot, s_wflag, wpre, wpref, agg, aggf);
   carry_t off = Op::czero();
   if constexpr (LOCAL) {

@@ -6,6 +6,31 @@ int check_dtype(int dtype) { return (dtype >= 0 && dtype <= 2) ? kOk : kInvalid;
 
 int check_flags(uint32_t flags) { return (flags & ~kKnownFlags) ? kInvalid : kOk; }
 
+int kernel_kind(int dtype, uint32_t flags) {
+  switch (op_of(flags)) {
+    case kOpSum: return dtype == 2 ? 1 : 0;
+    case kOpMax:
+    case kOpMin: return 2;
+    default: return 3;
+  }
+}
+
+uint32_t op_key(int dtype, uint32_t flags) {
+  const bool sgn = dtype == 0;
+  switch (op_of(flags)) {
+    case kOpMax: return sgn ? 0x80000000u : 0u;
+    case kOpMin: return sgn ? 0x7FFFFFFFu : 0xFFFFFFFFu;
+    default: return 0u;
+  }
+}
+
+int check_operator(int dtype, uint32_t flags) {
+  if (op_of(flags) == kOpSum) return kOk;
+  if (dtype == 2) return kNotSupported;
+  if ((flags & kFlagReverse) && op_key(dtype, flags) != 0u) return kNotSupported;
+  return kOk;
+}
+
 int check_flat(const void *in, const void *out, int64_t n) {
   if (n < 0) return kInvalid;
   if (n == 0) return kOk;

@@ -13,7 +13,22 @@ enum Status : int {
 
 constexpr uint32_t kFlagExclusive = 0x1u;
 constexpr uint32_t kFlagReverse = 0x2u;
-constexpr uint32_t kKnownFlags = kFlagExclusive | kFlagReverse;
+constexpr uint32_t kOpShift = 2;               // operator field: bits 2-3
+constexpr uint32_t kOpMask = 0x3u << kOpShift;
+enum Operator : uint32_t { kOpSum = 0, kOpMax = 1, kOpMin = 2, kOpXor = 3 };
+constexpr uint32_t kKnownFlags = kFlagExclusive | kFlagReverse | kOpMask;
+
+inline uint32_t op_of(uint32_t flags) { return (flags & kOpMask) >> kOpShift; }
+// Kernel kind for (dtype, operator): 0 integer sum, 1 float32 sum, 2 keyed
+// max (max and min), 3 xor.
+int kernel_kind(int dtype, uint32_t flags);
+// Key of the keyed max: the order (anti-)isomorphism x -> x ^ key that turns
+// the operator into an unsigned max with identity 0.
+uint32_t op_key(int dtype, uint32_t flags);
+// Operator combinations the kernels do not provide: max / min / xor of
+// float32, and a reverse scan whose identity is not 0 before keying (the
+// buffer loads beyond n return 0, which a reverse scan meets first).
+int check_operator(int dtype, uint32_t flags);
 
 // dtype: 0 = i32, 1 = u32, 2 = f32
 int check_dtype(int dtype);

@@ -21,8 +21,14 @@ def _stream(dev: torch.device):
     return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
 
 
-def _flags(exclusive: bool, reverse: bool) -> int:
-    return (SCAN_EXCLUSIVE if exclusive else 0) | (SCAN_REVERSE if reverse else 0)
+# operator field of the flags (bits 2-3): + (default), max, min, xor
+OPERATORS = {"sum": 0x0, "max": 0x4, "min": 0x8, "xor": 0xC}
+
+
+def _flags(exclusive: bool, reverse: bool, op: str = "sum") -> int:
+    if op not in OPERATORS:
+        raise ValueError("op must be one of %s" % sorted(OPERATORS))
+    return (SCAN_EXCLUSIVE if exclusive else 0) | (SCAN_REVERSE if reverse else 0) | OPERATORS[op]
 
 
 def _check_tensor(x: torch.Tensor, name: str) -> int:
@@ -55,15 +61,17 @@ def _check_offsets(offsets: torch.Tensor, x: torch.Tensor) -> int:
     return offsets.numel() - 1
 
 
-def cumsum(x: torch.Tensor, exclusive: bool = False, reverse: bool = False, out=None) -> torch.Tensor:
+def cumsum(x: torch.Tensor, exclusive: bool = False, reverse: bool = False, out=None,
+           op: str = "sum") -> torch.Tensor:
     """Scan of a contiguous int32 / uint32 / float32 GPU tensor (flattened).
 
-    out may be x itself (in place)."""
+    op: "sum" (any dtype), or "max" / "min" / "xor" for int32 (signed) and
+    uint32.  out may be x itself (in place)."""
     dt = _check_tensor(x, "x")
     out = _out_like(x, out)
     with torch.cuda.device(x.device):
         check(lib.scan_flat(x.data_ptr(), out.data_ptr(), x.numel(), dt,
-                            _flags(exclusive, reverse), _stream(x.device)), "scan_flat")
+                            _flags(exclusive, reverse, op), _stream(x.device)), "scan_flat")
     return out
 
 
@@ -72,14 +80,15 @@ def exclusive_cumsum(x: torch.Tensor, out=None) -> torch.Tensor:
 
 
 def segmented_scan(x: torch.Tensor, offsets: torch.Tensor, exclusive: bool = False,
-                   reverse: bool = False, out=None) -> torch.Tensor:
-    """Independent scans of the segments x[offsets[s]:offsets[s+1]] in one launch."""
+                   reverse: bool = False, out=None, op: str = "sum") -> torch.Tensor:
+    """Independent scans of the segments x[offsets[s]:offsets[s+1]] in one launch
+    (op as for cumsum)."""
     dt = _check_tensor(x, "x")
     S = _check_offsets(offsets, x)
     out = _out_like(x, out)
     with torch.cuda.device(x.device):
         check(lib.scan_segmented_batch(x.data_ptr(), out.data_ptr(), offsets.data_ptr(), S,
-                                       x.numel(), dt, _flags(exclusive, reverse),
+                                       x.numel(), dt, _flags(exclusive, reverse, op),
                                        _stream(x.device)), "scan_segmented_batch")
     return out
 

@@ -264,3 +264,102 @@ def pin_f32_segmented(seg_f32) -> list:
             s, _ = seg_f32(a, off, ex, rev)
             _fcmp("seg f ex=%d rev=%d" % (ex, rev), s, np.concatenate(want), fails)
     return fails
+
+
+# ---------------------------------------------------------------- other operators
+
+_IDENT = {("max", True): -(1 << 31), ("max", False): 0,
+          ("min", True): (1 << 31) - 1, ("min", False): M32 - 1, ("xor", True): 0, ("xor", False): 0}
+
+
+def _brute_op(a, op, exclusive, reverse):
+    """O(n^2) scan from the definition in Python integers: the reduction of
+    each prefix (suffix for reverse), starting from the operator's identity;
+    int32 compares as signed, uint32 as unsigned."""
+    sgn = np.asarray(a).dtype == np.int32
+    vals = [int(x) for x in a]
+    n = len(vals)
+    out = []
+    for i in range(n):
+        if not reverse:
+            idx = range(0, i) if exclusive else range(0, i + 1)
+        else:
+            idx = range(i + 1, n) if exclusive else range(i, n)
+        acc = _IDENT[(op, sgn)]
+        for j in idx:
+            x = vals[j]
+            acc = max(acc, x) if op == "max" else min(acc, x) if op == "min" else (acc ^ x)
+        out.append(acc)
+    return out
+
+
+def pin_int_operators(scan_op) -> list:
+    """scan_op(a, op, exclusive, reverse) for op in max / min / xor."""
+    fails = []
+    g = golden_io.load("operators_small.txt")
+    a = np.array(g["input"], dtype=np.int32)
+    for key, op, ex, rev in (("max_inclusive", "max", False, False), ("max_exclusive", "max", True, False),
+                             ("min_inclusive", "min", False, False), ("min_exclusive", "min", True, False),
+                             ("max_reverse", "max", False, True), ("xor_inclusive", "xor", False, False),
+                             ("xor_exclusive", "xor", True, False)):
+        _cmp("golden " + key, scan_op(a, op, ex, rev), g[key], fails)
+    u = a.view(np.uint32)
+    _cmp("golden umax_inclusive", scan_op(u, "max", False, False), g["umax_inclusive"], fails)
+    _cmp("golden umin_inclusive", scan_op(u, "min", False, False), g["umin_inclusive"], fails)
+
+    # brute force from the definition, both signednesses, every form
+    rng = np.random.default_rng(77)
+    for dt in (np.int32, np.uint32):
+        for n in (1, 2, 9, 40):
+            x = rng.integers(np.iinfo(dt).min, np.iinfo(dt).max, size=n, dtype=np.int64, endpoint=True).astype(dt)
+            for op in ("max", "min", "xor"):
+                for ex in (False, True):
+                    for rev in (False, True):
+                        _cmp("brute %s %s n=%d ex=%d rev=%d" % (op, np.dtype(dt).name, n, ex, rev),
+                             scan_op(x, op, ex, rev), _brute_op(x, op, ex, rev), fails)
+
+    # numpy's own cumulative reductions (signed compare for int32, unsigned for uint32)
+    for dt in (np.int32, np.uint32):
+        x = rng.integers(np.iinfo(dt).min, np.iinfo(dt).max, size=20000, dtype=np.int64, endpoint=True).astype(dt)
+        for op, uf in (("max", np.maximum), ("min", np.minimum), ("xor", np.bitwise_xor)):
+            _cmp("numpy %s.accumulate %s" % (op, np.dtype(dt).name), scan_op(x, op, False, False),
+                 uf.accumulate(x), fails)
+            _cmp("numpy reversed %s %s" % (op, np.dtype(dt).name), scan_op(x, op, False, True),
+                 uf.accumulate(x[::-1])[::-1], fails)
+
+    # invariants and special cases
+    x = rng.integers(-1000, 1000, size=5000).astype(np.int32)
+    inc = np.asarray(scan_op(x, "xor", False, False))
+    if not np.array_equal(np.bitwise_xor(inc[1:], inc[:-1]), x[1:]):
+        fails.append("xor: consecutive inclusive values must differ by the input")
+    for op in ("max", "min", "xor"):
+        inc = np.asarray(scan_op(x, op, False, False))
+        exc = np.asarray(scan_op(x, op, True, False))
+        if exc[0] != _IDENT[(op, True)] or not np.array_equal(exc[1:], inc[:-1]):
+            fails.append("%s: exclusive must be the identity then the inclusive shifted" % op)
+    srt = np.sort(x)
+    _cmp("max of ascending input = input", scan_op(srt, "max", False, False), srt, fails)
+    _cmp("min of ascending input = first", scan_op(srt, "min", False, False), [int(srt[0])] * srt.size, fails)
+    c = np.full(17, -5, dtype=np.int32)
+    _cmp("max of a constant", scan_op(c, "max", False, False), c, fails)
+    return fails
+
+
+def pin_int_operators_segmented(seg_op) -> list:
+    """seg_op(a, offsets, op, exclusive, reverse): per-segment scans from the
+    definition, empty segments included; one segment = the flat scan."""
+    fails = []
+    rng = np.random.default_rng(78)
+    a = rng.integers(-50, 50, size=30).astype(np.int32)
+    off = np.array([0, 0, 4, 5, 5, 13, 29, 30], dtype=np.int64)
+    for op in ("max", "min", "xor"):
+        for ex in (False, True):
+            for rev in (False, True):
+                want = []
+                for s in range(off.size - 1):
+                    want += _brute_op(a[off[s]:off[s + 1]], op, ex, rev)
+                _cmp("segmented brute %s ex=%d rev=%d" % (op, ex, rev), seg_op(a, off, op, ex, rev), want, fails)
+    x = rng.integers(0, 1 << 20, size=3000).astype(np.uint32)
+    _cmp("one segment = numpy max.accumulate", seg_op(x, np.array([0, x.size]), "max", False, False),
+         np.maximum.accumulate(x), fails)
+    return fails

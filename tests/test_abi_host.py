@@ -45,7 +45,7 @@ INVALID, OVERLAP = 1, 2
     ((None, None, 10, 0, 0), INVALID),          # null pointers
     ((4096, 8192, -1, 0, 0), INVALID),          # n < 0
     ((4096, 8192, 10, 3, 0), INVALID),          # unknown dtype
-    ((4096, 8192, 10, 0, 4), INVALID),          # unknown flag
+    ((4096, 8192, 10, 0, 0x10), INVALID),       # unknown flag
     ((4098, 8192, 10, 0, 0), INVALID),          # misaligned (needs 4 bytes)
     ((4096, 4100, 10, 0, 0), OVERLAP),          # partial overlap
     ((4100, 4096, 10, 2, 1), OVERLAP),
@@ -70,6 +70,29 @@ def test_segmented_argument_errors():
     assert f(4096, 8192, 16, 0, 10, 0, 0, None) == INVALID          # S = 0 with n > 0
     assert f(4096, 8192, 20, 3, 10, 0, 0, None) == INVALID          # offsets misaligned
     assert f(4096, 4100, 16, 3, 10, 0, 0, None) == OVERLAP
+
+
+NOT_SUPPORTED = 5
+OP_MAX, OP_MIN, OP_XOR, REV, EXC = 0x4, 0x8, 0xC, 0x2, 0x1
+
+
+@pytest.mark.parametrize("dtype,flags", [
+    (2, OP_MAX), (2, OP_MIN), (2, OP_XOR),       # float32 takes + only
+    (0, OP_MIN | REV), (1, OP_MIN | REV),        # reverse with a nonzero identity
+    (0, OP_MAX | REV),
+])
+def test_operator_not_supported(dtype, flags):
+    L = _lib()
+    assert L.lib.scan_flat(4096, 8192, 10, dtype, flags, None) == NOT_SUPPORTED
+    assert L.lib.scan_segmented_batch(4096, 8192, 16, 1, 10, dtype, flags, None) == NOT_SUPPORTED
+
+
+def test_operator_argument_errors_first():
+    L = _lib()
+    # bad arguments are reported before an unsupported operator combination
+    assert L.lib.scan_flat(None, None, 10, 2, OP_MAX, None) == INVALID
+    assert L.lib.scan_flat(None, None, 0, 0, OP_MAX | EXC, None) == 0
+    assert L.lib.scan_two_pass(4096, 8192, 10, 0, OP_XOR, 1, 0, None) == NOT_SUPPORTED
 
 
 def test_two_pass_argument_errors():

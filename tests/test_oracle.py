@@ -47,6 +47,15 @@ def test_oracle_f32_segmented_pinned():
     assert pins.pin_f32_segmented(_segf) == []
 
 
+def test_oracle_operators_pinned():
+    assert pins.pin_int_operators(lambda a, op, ex, rev: oracle.scan_op(a, op, ex, rev)) == []
+
+
+def test_oracle_operators_segmented_pinned():
+    assert pins.pin_int_operators_segmented(
+        lambda a, off, op, ex, rev: oracle.segmented_op(a, off, op, ex, rev)) == []
+
+
 def test_tolerance_scale():
     s, ab = oracle.scan_f32(np.array([1.0, -3.0], dtype=np.float32))
     assert np.array_equal(oracle.f32_tolerance(ab), np.array([1.0, 4.0]) * 2.0**-20)
@@ -145,3 +154,40 @@ def test_pins_catch_segmented_mutant(mutant):
 @pytest.mark.parametrize("mutant", [_m_f32_accumulator, _m_abs_signed])
 def test_pins_catch_f32_mutant(mutant):
     assert pins.pin_f32(mutant) != []
+
+
+# planted mistakes in the operator oracle
+def _m_op_unsigned_compare(a, op, ex, rev):
+    return oracle.scan_op(np.asarray(a).view(np.uint32), op, ex, rev).view(np.asarray(a).dtype)
+
+
+def _m_op_zero_identity(a, op, ex, rev):
+    out = np.asarray(oracle.scan_op(a, op, ex, rev)).copy()
+    if ex and out.size:
+        out[-1 if rev else 0] = 0
+    return out
+
+
+def _m_op_exclusive_is_inclusive(a, op, ex, rev):
+    return oracle.scan_op(a, op, False, rev)
+
+
+def _m_op_or_for_xor(a, op, ex, rev):
+    if op != "xor":
+        return oracle.scan_op(a, op, ex, rev)
+    v = np.asarray(a).view(np.uint32)
+    v = v[::-1] if rev else v
+    out = np.bitwise_or.accumulate(v) if v.size else v
+    if ex:
+        out = np.concatenate([[0], out[:-1]]).astype(np.uint32)
+    return (out[::-1] if rev else out).view(np.asarray(a).dtype)
+
+
+def _m_op_reverse_ignored(a, op, ex, rev):
+    return oracle.scan_op(a, op, ex, False)
+
+
+@pytest.mark.parametrize("mutant", [_m_op_unsigned_compare, _m_op_zero_identity, _m_op_exclusive_is_inclusive,
+                                    _m_op_or_for_xor, _m_op_reverse_ignored])
+def test_pins_catch_operator_mutant(mutant):
+    assert pins.pin_int_operators(mutant) != []
