@@ -137,6 +137,25 @@ scan_status_t scan_two_pass(const void *in, void *out, int64_t n, scan_dtype_t d
                             uint32_t flags, int32_t method, int64_t partition,
                             hipStream_t stream);
 
+/* ---- stream compaction fused with the exclusive scan ----
+ * The Introduction's use of prefix sums as new index values (partitioning,
+ * parallel filtering): out receives, in order, the elements of in[0..n) that
+ * the predicate keeps -- element i goes to out[e_i], e_i = the number of kept
+ * elements before i, i.e. the exclusive scan of the 0/1 selection -- and
+ * *count the number kept.  One pass over in; out[*count .. n) is left as it
+ * was.
+ * predicate: SCAN_PRED_NONZERO keeps elements whose 32 bits are not all zero
+ *   (threshold ignored); SCAN_PRED_GREATER keeps x > threshold, compared as
+ *   int32, uint32 or float32 by dtype (threshold holds the value's bits; a NaN
+ *   is never kept).
+ * in, out: n elements (in == out allowed); count: device int64, 8-byte
+ * aligned, written by the kernel.  n < 2^32.  Uses the stream's workspace. */
+#define SCAN_PRED_NONZERO 0
+#define SCAN_PRED_GREATER 1
+scan_status_t scan_compact(const void *in, void *out, int64_t n, scan_dtype_t dtype,
+                           int32_t predicate, uint32_t threshold, int64_t *count,
+                           hipStream_t stream);
+
 /* ---- float32 cumsum backward ----
  * For y = inclusive cumsum of x (per segment if offsets != NULL), the
  * gradient is the suffix sum of the upstream gradient:

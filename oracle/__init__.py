@@ -54,6 +54,8 @@ def _load():
         lib.oracle_segmented_f32_f64.argtypes = [P, P, P, P, I64, I, I]
         lib.oracle_scan_op_u32.argtypes = [P, P, I64, I, I, I, I]
         lib.oracle_segmented_op_u32.argtypes = [P, P, P, I64, I, I, I, I]
+        lib.oracle_compact_u32.argtypes = [P, P, I64, I, I, ctypes.c_uint32]
+        lib.oracle_compact_u32.restype = I64
         for f in (lib.oracle_scan_u32, lib.oracle_scan_f32_f64,
                   lib.oracle_segmented_u32, lib.oracle_segmented_f32_f64,
                   lib.oracle_scan_op_u32, lib.oracle_segmented_op_u32):
@@ -156,6 +158,22 @@ def segmented_op(a: np.ndarray, offsets: np.ndarray, op: str, exclusive: bool = 
     _load().oracle_segmented_op_u32(_ptr(src), _ptr(dst), _ptr(off), off.size - 1, OPERATORS[op],
                                     int(np.asarray(a).dtype == np.int32), int(exclusive), int(reverse))
     return dst.view(np.asarray(a).dtype)
+
+
+PREDICATES = {"nonzero": 0, "greater": 1}
+
+
+def compact(a: np.ndarray, predicate: str = "nonzero", threshold=0) -> np.ndarray:
+    """The elements of a (int32 / uint32 / float32) that the predicate keeps,
+    in order: "nonzero" (32 bits not all zero) or "greater" (x > threshold in
+    a's type; NaN never kept)."""
+    a = np.ascontiguousarray(a)
+    dt = {np.dtype(np.int32): 0, np.dtype(np.uint32): 1, np.dtype(np.float32): 2}[a.dtype]
+    thr = np.array([threshold], dtype=a.dtype).view(np.uint32)[0]
+    src = a.view(np.uint32)
+    dst = np.empty_like(src)
+    k = _load().oracle_compact_u32(_ptr(src), _ptr(dst), src.size, PREDICATES[predicate], dt, int(thr))
+    return dst[:k].view(a.dtype).copy()
 
 
 def f32_tolerance(abs_sums: np.ndarray) -> np.ndarray:

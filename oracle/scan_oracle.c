@@ -37,6 +37,7 @@
  */
 #include <stdint.h>
 #include <math.h>
+#include <string.h>
 
 /* ---- other operators ---------------------------------------------------
  * The Introduction defines the scan for any associative operator with an
@@ -160,4 +161,36 @@ void oracle_segmented_f32_f64(const float *a, double *out, double *abs_out,
             oracle_scan_f32_f64(a + lo, out + lo, abs_out ? abs_out + lo : 0,
                                 hi - lo, exclusive, reverse);
     }
+}
+
+/* ---- stream compaction ---------------------------------------------------
+ * The Introduction's partitioning / filtering use of the exclusive scan:
+ * element i is kept when the predicate holds and then written to out[e_i],
+ * e_i = the number of kept elements before i (the exclusive scan of the 0/1
+ * selection).  Sequentially that is: append each kept element in order.
+ * pred 0: keep x != 0 (its 32 bits); pred 1: keep x > thr compared as
+ * int32 (dtype 0), uint32 (dtype 1) or float32 (dtype 2; NaN is never kept).
+ * Returns the number kept; out[count..n) is not written. */
+static int oracle_keep(uint32_t x, int pred, int dtype, uint32_t thr)
+{
+    if (pred == 0) return x != 0u;
+    if (dtype == 0) return (int32_t)x > (int32_t)thr;
+    if (dtype == 1) return x > thr;
+    {
+        float fx, ft;
+        memcpy(&fx, &x, 4);
+        memcpy(&ft, &thr, 4);
+        return fx > ft;
+    }
+}
+
+int64_t oracle_compact_u32(const uint32_t *a, uint32_t *out, int64_t n, int pred,
+                           int dtype, uint32_t thr)
+{
+    int64_t k = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t x = a[i];
+        if (oracle_keep(x, pred, dtype, thr)) out[k++] = x;
+    }
+    return k;
 }

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libmi355scan.so")
 SCAN_I32, SCAN_U32, SCAN_F32 = 0, 1, 2
 SCAN_EXCLUSIVE, SCAN_REVERSE = 0x1, 0x2
 SCAN_TWO_PASS_PREFIX_INCREMENT, SCAN_TWO_PASS_ACCUMULATE_PREFIX = 0, 1
+SCAN_PRED_NONZERO, SCAN_PRED_GREATER = 0, 1
 
 STATUS_NAMES = {
     0: "SCAN_SUCCESS", 1: "SCAN_ERROR_INVALID_VALUE", 2: "SCAN_ERROR_OVERLAP",
@@ -43,6 +44,7 @@ SIGNATURES = {
     "scan_flat": (ST, [P, P, I64, ST, U32, P]),
     "scan_segmented_batch": (ST, [P, P, P, I32, I64, ST, U32, P]),
     "scan_two_pass": (ST, [P, P, I64, ST, U32, I32, I64, P]),
+    "scan_compact": (ST, [P, P, I64, ST, I32, U32, P, P]),
     "scan_f32_backward": (ST, [P, P, I64, P, I32, P]),
     "scan_reserve": (ST, [I64, P]),
     "scan_release": (ST, [P]),

@@ -1,0 +1,126 @@
+// Stream compaction fused with the exclusive scan: the Introduction's main
+// use of prefix sums -- the exclusive scan of a 0/1 selection gives every
+// kept element its index in the output (the partitioning / parallel
+// filtering use).  One pass: each tile is loaded once, its selection is
+// counted and scanned in registers, the tile's carry (number of elements
+// kept before it) comes from the same decoupled look-back as the scan, and
+// the kept elements are written to their final places.  HBM traffic: 4 bytes
+// read per element plus 4 written per kept element.
+#pragma once
+#include "scan_device.hpp"
+
+namespace mi355scan {
+
+__device__ __forceinline__ bool keep_element(uint32_t x, const CompactArgs &a) {
+  if (a.pred == kPredNonzero) return x != 0u;
+  if (a.dtype == 0) return (int32_t)x > (int32_t)a.thr;
+  if (a.dtype == 1) return x > a.thr;
+  return __builtin_bit_cast(float, x) > __builtin_bit_cast(float, a.thr);   // NaN never kept
+}
+
+// One tile per iteration of a resident grid (tiles from the device counter,
+// the workspace protocol of scan_tiles).  Per chunk each lane keeps a 4-bit
+// selection mask (8 chunks per register) and the wave-local number of kept
+// elements before its group; the values stay in R until they are written.
+template <int BLOCK, int ITEMS, bool VEC, int MINW>
+__global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
+  using SH = Shape<BLOCK, ITEMS>;
+  using Op = OpsU32;
+  constexpr int K = 4;
+  constexpr int MW = (SH::CH + 7) / 8;   // mask words
+  __shared__ uint32_t s_wtot[SH::WAVES];
+  __shared__ uint32_t s_wflag[SH::WAVES];
+  __shared__ uint32_t s_carry;
+  __shared__ int64_t s_tile;
+  __shared__ uint32_t s_parity;
+  const KernelArgs &ka = a.k;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = wave_id();
+  const bool multi = ka.tiles > 1;
+  uint32_t parity = 0;
+  int64_t t = 0;
+  if (multi) {
+    if (wave == 0) {
+      parity = readlane32(lane == 0 ? ld_agent32(&ka.hdr->parity) : 0u, 0);
+      t = acquire_tile(ka, parity, lane);
+      if (lane == 0) {
+        s_parity = parity;
+        s_tile = t;
+      }
+    }
+    __syncthreads();
+    parity = s_parity;
+    t = s_tile;
+  }
+  while (t < ka.tiles) {
+    u32x4 R[SH::CH];
+    {
+      const WaveSpan<SH, true, false, VEC> in(ka.in, ka, t, wave, lane);
+#pragma unroll
+      for (int c = 0; c < SH::CH; ++c) in.load(c, R[c]);
+    }
+    // elements of this lane's group in chunk c exist while c*256 + k < rem
+    const int64_t wb = wave_base<false, SH::TILE, SH::WSPAN>(t * (int64_t)SH::TILE, wave);
+    const int64_t rem64 = ka.n - wb - 4 * lane;
+    const int rem = rem64 > SH::WSPAN ? SH::WSPAN : (int)rem64;
+    uint32_t mask[MW];
+    uint32_t off[SH::CH];
+    uint32_t wsum = 0u;
+#pragma unroll
+    for (int w = 0; w < MW; ++w) mask[w] = 0u;
+#pragma unroll
+    for (int c = 0; c < SH::CH; ++c) {
+      uint32_t m = 0u;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) m |= (c * 256 + k < rem && keep_element(R[c][k], a)) ? (1u << k) : 0u;
+      mask[c / 8] |= m << (4 * (c % 8));
+      const uint32_t x = wave_scan<Op>((uint32_t)__builtin_popcount(m));
+      off[c] = wsum + lane_up1(x);
+      wsum += readlane32(x, 63);
+    }
+    uint32_t wpre, agg, wpref, aggf;
+    combine_waves<Op, SH::WAVES>(wave, lane, wsum, 0u, s_wtot, s_wflag, wpre, wpref, agg, aggf);
+    if (multi && wave == 0) {
+      uint64_t *st = ka.status + parity * ka.capacity;
+      publish_first<Op>(st, t, agg, 0u);
+      uint32_t carry = 0u;
+      if (t > 0) {
+        uint64_t w[K];
+        lb_window<Op, K>(st, (int32_t)t - 1, w);
+        carry = look_back<Op, K>(st, t, ka.spin_limit, ka.hdr, w);
+        if (lane == 0) st_agent(st + t, Op::pack(carry + agg, kPrefix));
+      }
+      if (lane == 0) s_carry = carry;
+    }
+    __syncthreads();
+    const uint32_t carry = t > 0 ? s_carry : 0u;
+    if (t == ka.tiles - 1 && tid == 0) *a.count = (int64_t)(carry + agg);
+    // kept elements go to out[carry + wpre + off[c] + (kept before k in the group)]
+    const uint32_t base = carry + wpre;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        static_cast<uint32_t *>(ka.out) + base, (short)0,
+        (int)((ka.n - (int64_t)base) * 4 > 0x7fffffff ? 0x7fffffff : (ka.n - (int64_t)base) * 4), 0x00020000);
+#pragma unroll
+    for (int c = 0; c < SH::CH; ++c) {
+      const uint32_t m = (mask[c / 8] >> (4 * (c % 8))) & 0xfu;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if ((m >> k) & 1u) {
+          const uint32_t pos = off[c] + (uint32_t)__builtin_popcount(m & ((1u << k) - 1u));
+          __builtin_amdgcn_raw_buffer_store_b32(R[c][k], rs, 4u * pos, 0, kNtAux);
+        }
+      }
+    }
+    if (!multi) break;
+    // next tile (the workgroup's stores above need no ordering with it)
+    if (wave == 0) {
+      const int64_t tk = acquire_tile(ka, parity, lane);
+      if (lane == 0) s_tile = tk;
+    }
+    __syncthreads();
+    t = s_tile;
+  }
+}
+
+}  // namespace mi355scan

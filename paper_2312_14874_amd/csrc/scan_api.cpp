@@ -433,6 +433,60 @@ scan_status_t two_pass(const void *in, void *out, int64_t n, scan_dtype_t dt, ui
   return SCAN_SUCCESS;
 }
 
+// Stream compaction fused with the exclusive scan: one resident launch over
+// 16384-element tiles (tiles from the counter, as the scan's mode 1).
+scan_status_t compact(const void *in, void *out, int64_t n, scan_dtype_t dt, int32_t predicate,
+                      uint32_t threshold, int64_t *count, hipStream_t stream) {
+  int r = check_dtype((int)dt);
+  if (r == kOk) r = check_flat(in, out, n);
+  if (r != kOk) return st(r);
+  if (!count || ((uintptr_t)count & 7u)) return SCAN_ERROR_INVALID_VALUE;
+  if (predicate != SCAN_PRED_NONZERO && predicate != SCAN_PRED_GREATER) return SCAN_ERROR_INVALID_VALUE;
+  if (n > (int64_t)0xFFFFFFFF) return SCAN_ERROR_NOT_SUPPORTED;   // counts are 32-bit
+  ensure_init();
+  int dev = 0;
+  DeviceInfo di;
+  scan_status_t s = current_device(&dev, &di);
+  if (s != SCAN_SUCCESS) return s;
+  const CompactKernels &K = kCompact;
+  if (n == 0) {
+    int64_t zero = 0;
+    void *zargs[] = {&count, &zero};
+    hipError_t e = hipLaunchKernel(K.set_count, dim3(1), dim3(1), zargs, 0, stream);
+    return e == hipSuccess ? SCAN_SUCCESS : hip_fail(e);
+  }
+  const int64_t tile = (int64_t)K.block * K.items;
+  const int64_t T = tiles_for(n, tile);
+  Workspace *ws = nullptr;
+  if (T > 1) {
+    s = stream_ws(dev, stream, T, &ws);
+    if (s != SCAN_SUCCESS) return s;
+  }
+  const void *fn = K.tiles[((uintptr_t)in & 15u) == 0 ? 1 : 0];
+  const int64_t grid = std::min<int64_t>(T, resident_grid(fn, K.block, di.cus, 0, 100));
+  CompactArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.k.in = in;
+  a.k.out = out;
+  a.k.n = n;
+  a.k.tiles = T;
+  a.k.hdr = ws ? ws->hdr : nullptr;
+  a.k.status = ws ? ws->status : nullptr;
+  a.k.capacity = ws ? ws->capacity : 0;
+  a.k.total_acquires = (uint64_t)(T + grid);   // every workgroup also takes one tile past the end
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    a.k.spin_limit = g_spin_limit;
+  }
+  a.count = count;
+  a.thr = threshold;
+  a.pred = predicate;
+  a.dtype = (int32_t)dt;
+  void *args[] = {&a};
+  hipError_t e = hipLaunchKernel(fn, dim3((unsigned)grid), dim3(K.block), args, 0, stream);
+  return e == hipSuccess ? SCAN_SUCCESS : hip_fail(e);
+}
+
 // Per-segment launches (comparator).  host_offsets are host memory.
 scan_status_t looped(const void *in, void *out, const int64_t *host_offsets, int32_t S,
                      scan_dtype_t dt, uint32_t flags, hipStream_t stream, Workspace *ws) {
@@ -654,6 +708,11 @@ scan_status_t scan_f32_backward(const float *grad_out, float *grad_in, int64_t n
 scan_status_t scan_two_pass(const void *in, void *out, int64_t n, scan_dtype_t dtype, uint32_t flags,
                             int32_t method, int64_t partition, hipStream_t stream) {
   return two_pass(in, out, n, dtype, flags, method, partition, stream);
+}
+
+scan_status_t scan_compact(const void *in, void *out, int64_t n, scan_dtype_t dtype, int32_t predicate,
+                           uint32_t threshold, int64_t *count, hipStream_t stream) {
+  return compact(in, out, n, dtype, predicate, threshold, count, stream);
 }
 
 scan_status_t scan_reserve(int64_t max_n, hipStream_t stream) {

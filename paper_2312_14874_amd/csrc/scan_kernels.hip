@@ -3,6 +3,7 @@
 #include "scan_device.hpp"
 #include "scan_table.hpp"
 #include "two_pass.hpp"
+#include "compact.hpp"
 
 namespace mi355scan {
 
@@ -95,6 +96,14 @@ const TwoPassKernels kTwoPass = {
      {MI355SCAN_TP(increment_tiles, OpsF32, true, false), MI355SCAN_TP(increment_tiles, OpsF32, true, true)}},
     {(const void *)&scan_totals<OpsU32>, (const void *)&scan_totals<OpsF32>},
     kTotalsBlock,
+};
+
+// stream compaction: 256 threads x 64 elements per tile, [vec]
+__global__ void set_count(int64_t *p, int64_t v) { *p = v; }
+const CompactKernels kCompact = {
+    256, 64,
+    {(const void *)&compact_tiles<256, 64, false, 3>, (const void *)&compact_tiles<256, 64, true, 3>},
+    (const void *)&set_count,
 };
 
 }  // namespace mi355scan

@@ -59,6 +59,19 @@ struct TwoPassArgs {
   int64_t ntiles;    // tiles in this partition
 };
 
+// Stream compaction: predicates (the selection is computed on the fly from
+// each element) and kernel arguments.
+constexpr int kPredNonzero = 0;   // keep x whose 32 bits are not all zero
+constexpr int kPredGreater = 1;   // keep x > threshold (typed compare)
+
+struct CompactArgs {
+  KernelArgs k;       // in, out, n, tiles, workspace, counter mode fields
+  int64_t *count;     // device: number of kept elements, written by the last tile
+  uint32_t thr;       // threshold bits (kPredGreater)
+  int32_t pred;       // kPred*
+  int32_t dtype;      // 0 int32, 1 uint32, 2 float32
+};
+
 // Ordered launches count published tiles in kPubSlots counters per parity
 // (spread over separate cache lines so their atomics do not serialise on one
 // address); the last tile waits for the count before handing over.

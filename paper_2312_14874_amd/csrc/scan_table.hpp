@@ -47,4 +47,12 @@ struct TwoPassKernels {
 };
 extern const TwoPassKernels kTwoPass;
 
+// Stream compaction fused with the exclusive scan, one tile shape.
+struct CompactKernels {
+  int block, items;
+  const void *tiles[2];    // [vec]
+  const void *set_count;   // writes the count when there is nothing to scan
+};
+extern const CompactKernels kCompact;
+
 }  // namespace mi355scan

@@ -9,8 +9,8 @@ import ctypes
 
 import torch
 
-from ._lib import (SCAN_EXCLUSIVE, SCAN_F32, SCAN_I32, SCAN_REVERSE, SCAN_TWO_PASS_ACCUMULATE_PREFIX,
-                   SCAN_TWO_PASS_PREFIX_INCREMENT, SCAN_U32, check, lib)
+from ._lib import (SCAN_EXCLUSIVE, SCAN_F32, SCAN_I32, SCAN_PRED_GREATER, SCAN_PRED_NONZERO, SCAN_REVERSE,
+                   SCAN_TWO_PASS_ACCUMULATE_PREFIX, SCAN_TWO_PASS_PREFIX_INCREMENT, SCAN_U32, check, lib)
 
 _DTYPES = {torch.int32: SCAN_I32, torch.float32: SCAN_F32}
 if hasattr(torch, "uint32"):
@@ -105,6 +105,35 @@ def segmented_scan_looped(x: torch.Tensor, host_offsets, exclusive: bool = False
                                         dt, _flags(exclusive, reverse), _stream(x.device)),
               "scan_segmented_looped")
     return out
+
+
+PREDICATES = {"nonzero": SCAN_PRED_NONZERO, "greater": SCAN_PRED_GREATER}
+
+
+def compact_into(x: torch.Tensor, out: torch.Tensor, count: torch.Tensor, predicate: str = "nonzero",
+                 threshold=0) -> None:
+    """Asynchronous stream compaction: out[:count] receives, in order, the
+    elements of x the predicate keeps ("nonzero", or "greater": x > threshold
+    in x's type); count is a one-element int64 GPU tensor."""
+    if predicate not in PREDICATES:
+        raise ValueError("predicate must be one of %s" % sorted(PREDICATES))
+    dt = _check_tensor(x, "x")
+    out = _out_like(x, out)
+    if count.dtype != torch.int64 or count.numel() != 1 or count.device != x.device:
+        raise ValueError("count must be a one-element int64 tensor on x's device")
+    thr = torch.tensor([threshold], dtype=x.dtype).view(torch.int32).item() & 0xFFFFFFFF
+    with torch.cuda.device(x.device):
+        check(lib.scan_compact(x.data_ptr(), out.data_ptr(), x.numel(), dt, PREDICATES[predicate], thr,
+                               count.data_ptr(), _stream(x.device)), "scan_compact")
+
+
+def compact(x: torch.Tensor, predicate: str = "nonzero", threshold=0) -> torch.Tensor:
+    """The elements of x the predicate keeps, in order (synchronises to read
+    the count)."""
+    out = torch.empty_like(x)
+    count = torch.empty(1, dtype=torch.int64, device=x.device)
+    compact_into(x, out, count, predicate, threshold)
+    return out[:int(count.item())]
 
 
 TWO_PASS_METHODS = {"prefix_increment": SCAN_TWO_PASS_PREFIX_INCREMENT,

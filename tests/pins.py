@@ -363,3 +363,42 @@ def pin_int_operators_segmented(seg_op) -> list:
     _cmp("one segment = numpy max.accumulate", seg_op(x, np.array([0, x.size]), "max", False, False),
          np.maximum.accumulate(x), fails)
     return fails
+
+
+# ---------------------------------------------------------------- stream compaction
+
+def pin_compact(compact) -> list:
+    """compact(a, predicate, threshold) -> kept elements in order."""
+    fails = []
+    g = golden_io.load("compact_small.txt")
+    a = np.array(g["input"], dtype=np.int32)
+    _cmp("golden nonzero", compact(a, "nonzero", 0), g["nonzero_kept"], fails)
+    _cmp("golden > 2", compact(a, "greater", 2), g["greater_2_kept"], fails)
+    _cmp("golden > -2", compact(a, "greater", -2), g["greater_minus2_kept"], fails)
+    # the kept elements sit at the exclusive scan of the selection (Python ints)
+    sel = [1 if x != 0 else 0 for x in g["input"]]
+    pos = [sum(sel[:i]) for i in range(len(sel))]
+    if pos != g["nonzero_positions"] or sel != g["nonzero_selection"]:
+        fails.append("fixture positions are not the exclusive scan of the selection")
+    rng = np.random.default_rng(90)
+    for dt in (np.int32, np.uint32):
+        x = rng.integers(np.iinfo(dt).min, np.iinfo(dt).max, size=5000, dtype=np.int64, endpoint=True).astype(dt)
+        x[rng.random(x.size) < 0.3] = 0
+        thr = dt(rng.integers(np.iinfo(dt).min // 2, np.iinfo(dt).max // 2))
+        _cmp("numpy mask nonzero %s" % np.dtype(dt).name, compact(x, "nonzero", 0), x[x != 0], fails)
+        _cmp("numpy mask greater %s" % np.dtype(dt).name, compact(x, "greater", thr), x[x > thr], fails)
+    f = rng.standard_normal(3000).astype(np.float32)
+    f[::97] = np.nan
+    got = np.asarray(compact(f, "greater", np.float32(0.25)))
+    want = f[f > np.float32(0.25)]
+    if got.shape != want.shape or not np.array_equal(got.view(np.uint32), want.view(np.uint32)):
+        fails.append("numpy mask float32 greater (NaN never kept)")
+    # special cases: nothing kept, everything kept (a copy), empty input
+    z = np.zeros(100, dtype=np.int32)
+    if np.asarray(compact(z, "nonzero", 0)).size != 0:
+        fails.append("all-zero input keeps nothing")
+    o = np.arange(1, 101, dtype=np.int32)
+    _cmp("everything kept = copy", compact(o, "greater", 0), o, fails)
+    if np.asarray(compact(np.zeros(0, dtype=np.int32), "nonzero", 0)).size != 0:
+        fails.append("empty input")
+    return fails

@@ -95,6 +95,18 @@ def test_operator_argument_errors_first():
     assert L.lib.scan_two_pass(4096, 8192, 10, 0, OP_XOR, 1, 0, None) == NOT_SUPPORTED
 
 
+def test_compact_argument_errors():
+    L = _lib()
+    f = L.lib.scan_compact
+    assert f(4096, 8192, 10, 0, 0, 0, None, None) == INVALID        # no count pointer
+    assert f(4096, 8192, 10, 0, 0, 0, 12, None) == INVALID          # count misaligned
+    assert f(4096, 8192, 10, 0, 2, 0, 16, None) == INVALID          # unknown predicate
+    assert f(None, None, 10, 0, 0, 0, 16, None) == INVALID          # null pointers
+    assert f(4096, 4100, 10, 0, 0, 0, 16, None) == OVERLAP
+    assert f(4096, 8192, 10, 3, 0, 0, 16, None) == INVALID          # unknown dtype
+    assert f(1 << 40, 1 << 41, 1 << 33, 0, 0, 0, 16, None) == NOT_SUPPORTED   # n >= 2^32
+
+
 def test_two_pass_argument_errors():
     L = _lib()
     f = L.lib.scan_two_pass

@@ -1,0 +1,87 @@
+"""Stream compaction fused with the exclusive scan against the oracle, bit-exact:
+both predicates, the three dtypes, selectivities from none to all, ragged
+sizes, in place, misaligned input, and the 2^28 workload size."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import DT, check_status, first_mismatch, from_dev, lib, stream, to_dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+PRED = {"nonzero": 0, "greater": 1}
+
+
+def run(a, predicate, threshold=0, misalign=0, inplace=False):
+    L = lib()
+    x = to_dev(a, pad=misalign + 4)
+    xin = x[misalign + 4:]
+    out = xin if inplace else torch.full((a.size + 4,), -1, dtype=x.dtype, device="cuda")[4:]
+    cnt = torch.full((1,), -1, dtype=torch.int64, device="cuda")
+    thr = int(np.array([threshold], dtype=a.dtype).view(np.uint32)[0])
+    check_status(L.scan_compact(xin.data_ptr(), out.data_ptr(), a.size, DT[a.dtype], PRED[predicate], thr,
+                                cnt.data_ptr(), stream()), "scan_compact")
+    torch.cuda.synchronize()
+    k = int(cnt.item())
+    return from_dev(out, a.dtype)[:k], k
+
+
+def data(n, seed, dtype, zero_frac=0.5):
+    g = np.random.default_rng(seed)
+    if dtype == np.float32:
+        a = g.standard_normal(n).astype(np.float32)
+    else:
+        a = g.integers(np.iinfo(dtype).min, np.iinfo(dtype).max, size=n, dtype=np.int64, endpoint=True).astype(dtype)
+    a[g.random(n) < zero_frac] = 0
+    return a
+
+
+def check(a, predicate, threshold=0, **kw):
+    want = oracle.compact(a, predicate, threshold)
+    got, k = run(a, predicate, threshold, **kw)
+    assert k == want.size, (k, want.size)
+    assert not first_mismatch(got.view(np.uint32), want.view(np.uint32))
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.uint32, np.float32])
+@pytest.mark.parametrize("n", [1, 100, 16383, 16384, 16385, 5 * 16384 + 777, 1 << 20])
+def test_nonzero(dtype, n):
+    check(data(n, 4000 + n % 89, dtype), "nonzero")
+
+
+@pytest.mark.parametrize("dtype,thr", [(np.int32, 0), (np.int32, -1 << 30), (np.uint32, 1 << 31),
+                                       (np.float32, 0.5), (np.float32, -3.0)])
+def test_greater(dtype, thr):
+    check(data(3 * 16384 + 99, 4100, dtype, zero_frac=0.1), "greater", thr)
+
+
+@pytest.mark.parametrize("zero_frac", [0.0, 1.0, 0.999, 0.001])
+def test_selectivity_extremes(zero_frac):
+    check(data(7 * 16384 + 5, 4200, np.int32, zero_frac=zero_frac), "nonzero")
+
+
+def test_nan_never_kept():
+    a = data(50000, 4300, np.float32)
+    a[::7] = np.nan
+    check(a, "greater", -1e30)
+
+
+def test_zero_length_writes_count():
+    L = lib()
+    cnt = torch.full((1,), -1, dtype=torch.int64, device="cuda")
+    check_status(L.scan_compact(None, None, 0, 0, 0, 0, cnt.data_ptr(), stream()), "scan_compact n=0")
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == 0
+
+
+def test_in_place_and_misaligned():
+    a = data(9 * 16384 + 321, 4400, np.int32)
+    check(a, "nonzero", inplace=True)
+    for mis in (1, 2, 3):
+        check(a, "nonzero", misalign=mis)
+
+
+def test_full_size():
+    a = data(1 << 28, 4500, np.int32, zero_frac=0.5)
+    check(a, "greater", 0)

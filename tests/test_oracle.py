@@ -56,6 +56,33 @@ def test_oracle_operators_segmented_pinned():
         lambda a, off, op, ex, rev: oracle.segmented_op(a, off, op, ex, rev)) == []
 
 
+def test_oracle_compact_pinned():
+    assert pins.pin_compact(lambda a, p, t: oracle.compact(a, p, t)) == []
+
+
+def _m_compact_keep_ge(a, p, t):
+    a = np.asarray(a)
+    if p == "greater":
+        return a[a >= np.array(t, dtype=a.dtype)]
+    return oracle.compact(a, p, t)
+
+
+def _m_compact_unsigned(a, p, t):
+    a = np.asarray(a)
+    if p == "greater" and a.dtype == np.int32:
+        return oracle.compact(a.view(np.uint32), p, np.array(t, dtype=np.int32).view(np.uint32)).view(np.int32)
+    return oracle.compact(a, p, t)
+
+
+def _m_compact_unordered(a, p, t):
+    return np.sort(np.asarray(oracle.compact(a, p, t)))
+
+
+@pytest.mark.parametrize("mutant", [_m_compact_keep_ge, _m_compact_unsigned, _m_compact_unordered])
+def test_pins_catch_compact_mutant(mutant):
+    assert pins.pin_compact(mutant) != []
+
+
 def test_tolerance_scale():
     s, ab = oracle.scan_f32(np.array([1.0, -3.0], dtype=np.float32))
     assert np.array_equal(oracle.f32_tolerance(ab), np.array([1.0, 4.0]) * 2.0**-20)
