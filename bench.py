@@ -25,6 +25,9 @@ resident in HBM.  Prints ONE JSON line on stdout; progress goes to stderr.
              against the single pass; results compared with its output
   operators  the same input scanned with max, min and xor (int32), kernel
              time from HIP events, each result checked against the oracle
+  compaction the same input read as int32, elements > 0 kept (about half)
+             by the fused one-pass compaction, against torch's masked select
+             for context; results checked against the oracle
 Extra modes (not the headline line): --n, --dtype f32, --copy-calibration.
 """
 from __future__ import annotations
@@ -85,6 +88,7 @@ def parse():
     p.add_argument("--no-segmented", action="store_true", help="skip the segmented comparison")
     p.add_argument("--no-two-pass", action="store_true", help="skip the two-pass comparison")
     p.add_argument("--no-operators", action="store_true", help="skip the max / min / xor scans")
+    p.add_argument("--no-compaction", action="store_true", help="skip the stream compaction")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run only plain device copies of the scan's bytes (counter calibration)")
     return p.parse_args()
@@ -216,6 +220,11 @@ def main():
     if not args.no_operators and args.dtype == "u32":
         ops = operator_runs(scan, torch, np, oracle, a, x, y, stream)
 
+    # ---------------------------------------------------------- stream compaction of the same input
+    comp = None
+    if not args.no_compaction and args.dtype == "u32":
+        comp = compaction_run(scan, torch, np, oracle, a, x, y, stream)
+
     del x, y
     traffic = measured_traffic(n) if args.dtype == "u32" else None
     out = {
@@ -243,8 +252,45 @@ def main():
         "segmented": seg,
         "two_pass": two,
         "operators": ops,
+        "compaction": comp,
     }
     print(json.dumps(out), flush=True)
+
+
+def compaction_run(scan, torch, np, oracle, a, x, y, stream):
+    """Elements > 0 of the bench input read as int32, fused one-pass compaction."""
+    n = x.numel()
+    cnt = torch.empty(1, dtype=torch.int64, device=x.device)
+
+    def run():
+        scan.compact_into(x, y, cnt, "greater", 0)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ts.sort()
+        return ts[len(ts) // 2]
+
+    ms = timed(run, 20)
+    k = int(cnt.item())
+    want = oracle.compact(a.view(np.int32), "greater", 0)
+    ok = k == want.size and np.array_equal(y[:k].cpu().numpy(), want)
+    ms_torch = timed(lambda: torch.masked_select(x, x > 0), 5)
+    moved = 4.0 * n + 4.0 * k
+    res = {"workload": "keep x > 0 of the same n=2^%d input read as int32 (%d kept)" % (n.bit_length() - 1, k),
+           "fused_us": round(ms * 1e3, 1), "GBps_moved": round(moved / (ms * 1e-3) / 1e9, 1),
+           "bytes_moved": int(moved), "torch_masked_select_us": round(ms_torch * 1e3, 1),
+           "speedup_vs_torch": round(ms_torch / ms, 2), "results_equal_oracle": bool(ok)}
+    log("compaction:", res)
+    return res
 
 
 def operator_runs(scan, torch, np, oracle, a, x, y, stream):

@@ -20,8 +20,13 @@ __device__ __forceinline__ bool keep_element(uint32_t x, const CompactArgs &a) {
 
 // One tile per iteration of a resident grid (tiles from the device counter,
 // the workspace protocol of scan_tiles).  Per chunk each lane keeps a 4-bit
-// selection mask (8 chunks per register) and the wave-local number of kept
-// elements before its group; the values stay in R until they are written.
+// selection mask (8 chunks per register) and the number of kept elements
+// before its group in the chunk; the chunk's offset in the wave is uniform.
+// The values stay in R until they are written: per chunk, the wave packs its
+// kept elements into its own LDS row and writes them out as one contiguous
+// run (dword stores of consecutive lanes) instead of one scattered store per
+// element; as in scan_tiles, the registers a packed chunk frees take the next
+// tile's chunk at once.
 template <int BLOCK, int ITEMS, bool VEC, int MINW>
 __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
   using SH = Shape<BLOCK, ITEMS>;
@@ -33,6 +38,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
   __shared__ uint32_t s_carry;
   __shared__ int64_t s_tile;
   __shared__ uint32_t s_parity;
+  __shared__ uint32_t s_stage[SH::WAVES][256];
   const KernelArgs &ka = a.k;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -53,19 +59,20 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
     parity = s_parity;
     t = s_tile;
   }
-  while (t < ka.tiles) {
-    u32x4 R[SH::CH];
-    {
-      const WaveSpan<SH, true, false, VEC> in(ka.in, ka, t, wave, lane);
+  u32x4 R[SH::CH];
+  if (t < ka.tiles) {
+    const WaveSpan<SH, true, false, VEC> in(ka.in, ka, t, wave, lane);
 #pragma unroll
-      for (int c = 0; c < SH::CH; ++c) in.load(c, R[c]);
-    }
+    for (int c = 0; c < SH::CH; ++c) in.load(c, R[c]);
+  }
+  while (t < ka.tiles) {
     // elements of this lane's group in chunk c exist while c*256 + k < rem
     const int64_t wb = wave_base<false, SH::TILE, SH::WSPAN>(t * (int64_t)SH::TILE, wave);
     const int64_t rem64 = ka.n - wb - 4 * lane;
     const int rem = rem64 > SH::WSPAN ? SH::WSPAN : (int)rem64;
     uint32_t mask[MW];
-    uint32_t off[SH::CH];
+    uint32_t off[SH::CH];    // kept elements before this lane's group in chunk c
+    uint32_t cbase[SH::CH];  // kept elements of the wave before chunk c (uniform)
     uint32_t wsum = 0u;
 #pragma unroll
     for (int w = 0; w < MW; ++w) mask[w] = 0u;
@@ -76,7 +83,8 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
       for (int k = 0; k < 4; ++k) m |= (c * 256 + k < rem && keep_element(R[c][k], a)) ? (1u << k) : 0u;
       mask[c / 8] |= m << (4 * (c % 8));
       const uint32_t x = wave_scan<Op>((uint32_t)__builtin_popcount(m));
-      off[c] = wsum + lane_up1(x);
+      off[c] = lane_up1(x);
+      cbase[c] = wsum;
       wsum += readlane32(x, 63);
     }
     uint32_t wpre, agg, wpref, aggf;
@@ -96,30 +104,63 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
     __syncthreads();
     const uint32_t carry = t > 0 ? s_carry : 0u;
     if (t == ka.tiles - 1 && tid == 0) *a.count = (int64_t)(carry + agg);
-    // kept elements go to out[carry + wpre + off[c] + (kept before k in the group)]
+    // kept elements go to out[carry + wpre + cbase[c] + off[c] + (kept before k in the group)]
     const uint32_t base = carry + wpre;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         static_cast<uint32_t *>(ka.out) + base, (short)0,
         (int)((ka.n - (int64_t)base) * 4 > 0x7fffffff ? 0x7fffffff : (ka.n - (int64_t)base) * 4), 0x00020000);
-#pragma unroll
-    for (int c = 0; c < SH::CH; ++c) {
+    uint32_t *stage = s_stage[wave];
+    // chunk c: pack the kept elements into the wave's LDS row (wave-private:
+    // no barrier; R[c] is free afterwards), then write them as one run
+    auto pack = [&](const int c) {
       const uint32_t m = (mask[c / 8] >> (4 * (c % 8))) & 0xfu;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if ((m >> k) & 1u) {
-          const uint32_t pos = off[c] + (uint32_t)__builtin_popcount(m & ((1u << k) - 1u));
-          __builtin_amdgcn_raw_buffer_store_b32(R[c][k], rs, 4u * pos, 0, kNtAux);
-        }
+      for (int k = 0; k < 4; ++k)
+        if ((m >> k) & 1u) stage[off[c] + (uint32_t)__builtin_popcount(m & ((1u << k) - 1u))] = R[c][k];
+    };
+    auto flush = [&](const int c) {
+      const uint32_t kept = (c + 1 < SH::CH ? cbase[c + 1] : wsum) - cbase[c];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t idx = 64u * j + lane;
+        if (idx < kept) __builtin_amdgcn_raw_buffer_store_b32(stage[idx], rs, 4u * (cbase[c] + idx), 0, kNtAux);
+      }
+    };
+    // the first half goes out while the next tile is taken from the counter,
+    // then each chunk's registers take the next tile's chunk once it is packed
+    constexpr int KH = SH::CH / 2;
+#pragma unroll
+    for (int c = 0; c < KH; ++c) {
+      pack(c);
+      flush(c);
+    }
+    int64_t next = ka.tiles;
+    if (multi) {
+      if (wave == 0) {
+        const int64_t tk = acquire_tile(ka, parity, lane);
+        if (lane == 0) s_tile = tk;
+      }
+      __syncthreads();
+      next = s_tile;
+    }
+    if (next < ka.tiles) {
+      const WaveSpan<SH, true, false, VEC> in(ka.in, ka, next, wave, lane);
+#pragma unroll
+      for (int c = KH; c < SH::CH; ++c) {
+        pack(c);
+        in.load(c - KH, R[c - KH]);
+        flush(c);
+      }
+#pragma unroll
+      for (int c = SH::CH - KH; c < SH::CH; ++c) in.load(c, R[c]);
+    } else {
+#pragma unroll
+      for (int c = KH; c < SH::CH; ++c) {
+        pack(c);
+        flush(c);
       }
     }
-    if (!multi) break;
-    // next tile (the workgroup's stores above need no ordering with it)
-    if (wave == 0) {
-      const int64_t tk = acquire_tile(ka, parity, lane);
-      if (lane == 0) s_tile = tk;
-    }
-    __syncthreads();
-    t = s_tile;
+    t = next;
   }
 }
 
