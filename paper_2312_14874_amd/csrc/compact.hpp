@@ -20,8 +20,8 @@ __device__ __forceinline__ bool keep_element(uint32_t x, const CompactArgs &a) {
 
 // One tile per iteration of a resident grid (tiles from the device counter,
 // the workspace protocol of scan_tiles).  Per chunk each lane keeps a 4-bit
-// selection mask (8 chunks per register) and the number of kept elements
-// before its group in the chunk; the chunk's offset in the wave is uniform.
+// selection mask (8 chunks per register); the tile total needs only the
+// lanes' counts, and a chunk's positions are scanned when it is written.
 // The values stay in R until they are written: per chunk, the wave packs its
 // kept elements into its own LDS row and writes them out as one contiguous
 // run (dword stores of consecutive lanes) instead of one scattered store per
@@ -70,10 +70,11 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
     const int64_t wb = wave_base<false, SH::TILE, SH::WSPAN>(t * (int64_t)SH::TILE, wave);
     const int64_t rem64 = ka.n - wb - 4 * lane;
     const int rem = rem64 > SH::WSPAN ? SH::WSPAN : (int)rem64;
+    // first pass: the selection masks and the number kept by the lane; the
+    // positions are recomputed per chunk when the chunk is written, so no
+    // per-chunk offsets are held through the look-back
     uint32_t mask[MW];
-    uint32_t off[SH::CH];    // kept elements before this lane's group in chunk c
-    uint32_t cbase[SH::CH];  // kept elements of the wave before chunk c (uniform)
-    uint32_t wsum = 0u;
+    uint32_t lane_kept = 0u;
 #pragma unroll
     for (int w = 0; w < MW; ++w) mask[w] = 0u;
 #pragma unroll
@@ -82,11 +83,9 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) m |= (c * 256 + k < rem && keep_element(R[c][k], a)) ? (1u << k) : 0u;
       mask[c / 8] |= m << (4 * (c % 8));
-      const uint32_t x = wave_scan<Op>((uint32_t)__builtin_popcount(m));
-      off[c] = lane_up1(x);
-      cbase[c] = wsum;
-      wsum += readlane32(x, 63);
+      lane_kept += (uint32_t)__builtin_popcount(m);
     }
+    const uint32_t wsum = readlane32(wave_scan<Op>(lane_kept), 63);
     uint32_t wpre, agg, wpref, aggf;
     combine_waves<Op, SH::WAVES>(wave, lane, wsum, 0u, s_wtot, s_wflag, wpre, wpref, agg, aggf);
     if (multi && wave == 0) {
@@ -104,36 +103,39 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
     __syncthreads();
     const uint32_t carry = t > 0 ? s_carry : 0u;
     if (t == ka.tiles - 1 && tid == 0) *a.count = (int64_t)(carry + agg);
-    // kept elements go to out[carry + wpre + cbase[c] + off[c] + (kept before k in the group)]
+    // kept elements go to out[carry + wpre + (kept in the wave's earlier
+    // chunks) + (kept in earlier lanes of the chunk) + (kept before k in the group)]
     const uint32_t base = carry + wpre;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         static_cast<uint32_t *>(ka.out) + base, (short)0,
         (int)((ka.n - (int64_t)base) * 4 > 0x7fffffff ? 0x7fffffff : (ka.n - (int64_t)base) * 4), 0x00020000);
     uint32_t *stage = s_stage[wave];
-    // chunk c: pack the kept elements into the wave's LDS row (wave-private:
-    // no barrier; R[c] is free afterwards), then write them as one run
-    auto pack = [&](const int c) {
+    uint32_t cb = 0u;   // kept in the wave's chunks so far (uniform)
+    // chunk c: scan the lanes' counts, pack the kept elements into the
+    // wave's LDS row (wave-private: no barrier; R[c] is free afterwards),
+    // write them as one contiguous run
+    auto pack = [&](const int c) -> uint32_t {
       const uint32_t m = (mask[c / 8] >> (4 * (c % 8))) & 0xfu;
+      const uint32_t x = wave_scan<Op>((uint32_t)__builtin_popcount(m));
+      const uint32_t off = lane_up1(x);
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        if ((m >> k) & 1u) stage[off[c] + (uint32_t)__builtin_popcount(m & ((1u << k) - 1u))] = R[c][k];
+        if ((m >> k) & 1u) stage[off + (uint32_t)__builtin_popcount(m & ((1u << k) - 1u))] = R[c][k];
+      return readlane32(x, 63);
     };
-    auto flush = [&](const int c) {
-      const uint32_t kept = (c + 1 < SH::CH ? cbase[c + 1] : wsum) - cbase[c];
+    auto flush = [&](const uint32_t kept) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const uint32_t idx = 64u * j + lane;
-        if (idx < kept) __builtin_amdgcn_raw_buffer_store_b32(stage[idx], rs, 4u * (cbase[c] + idx), 0, kNtAux);
+        if (idx < kept) __builtin_amdgcn_raw_buffer_store_b32(stage[idx], rs, 4u * (cb + idx), 0, kNtAux);
       }
+      cb += kept;
     };
     // the first half goes out while the next tile is taken from the counter,
     // then each chunk's registers take the next tile's chunk once it is packed
     constexpr int KH = SH::CH / 2;
 #pragma unroll
-    for (int c = 0; c < KH; ++c) {
-      pack(c);
-      flush(c);
-    }
+    for (int c = 0; c < KH; ++c) flush(pack(c));
     int64_t next = ka.tiles;
     if (multi) {
       if (wave == 0) {
@@ -147,18 +149,15 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
       const WaveSpan<SH, true, false, VEC> in(ka.in, ka, next, wave, lane);
 #pragma unroll
       for (int c = KH; c < SH::CH; ++c) {
-        pack(c);
+        const uint32_t kept = pack(c);
         in.load(c - KH, R[c - KH]);
-        flush(c);
+        flush(kept);
       }
 #pragma unroll
       for (int c = SH::CH - KH; c < SH::CH; ++c) in.load(c, R[c]);
     } else {
 #pragma unroll
-      for (int c = KH; c < SH::CH; ++c) {
-        pack(c);
-        flush(c);
-      }
+      for (int c = KH; c < SH::CH; ++c) flush(pack(c));
     }
     t = next;
   }
