@@ -41,6 +41,10 @@ struct OpsU32 {
   // registers, so it branches in smaller groups and keeps one carry add)
   static constexpr int kSegGroup = 4;
   static constexpr bool kSplitCarry = true;
+  // combine_waves folds the wave totals from one lane each (true) or reads
+  // each from LDS into registers of its own (false); measured per type: the
+  // float64 totals spill the 768 x 128 kernel in the second form
+  static constexpr bool kCombineByLane = false;
   __device__ static lane_t lzero() { return 0u; }
   __device__ static carry_t czero() { return 0u; }
   __device__ static lane_t ladd(lane_t a, lane_t b) { return a + b; }
@@ -69,6 +73,7 @@ struct OpsF32 {
   static constexpr bool kKeyed = false;
   static constexpr int kSegGroup = 2;
   static constexpr bool kSplitCarry = false;
+  static constexpr bool kCombineByLane = true;
   __device__ static lane_t lzero() { return 0.0f; }
   __device__ static carry_t czero() { return 0.0; }
   __device__ static lane_t ladd(lane_t a, lane_t b) { return a + b; }
@@ -636,19 +641,32 @@ __device__ __forceinline__ void scan_wave(uint32_t exclusive, uint32_t key, int 
   wflag_out = wflag;
 }
 
+// A wave-uniform copy of lane l's value (32- or 64-bit).
+template <class T>
+__device__ __forceinline__ T readlane_of(T x, int l) {
+  if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, readlane64(__builtin_bit_cast(uint64_t, x), l));
+  else return __builtin_bit_cast(T, readlane32(__builtin_bit_cast(uint32_t, x), l));
+}
+
 // Wave totals through LDS: this wave's exclusive prefix (wpre, wpref) and
 // the tile aggregate (agg, aggf), all folded left to right.  Contains one
-// barrier.
+// barrier.  With Op::kCombineByLane lane w reads wave w's total and the fold
+// runs on wave-uniform copies, so the waves' totals do not each take
+// registers of their own; otherwise every total is read from LDS.
 template <class Op, int WAVES>
 __device__ __forceinline__ void combine_waves(int wave, int lane, typename Op::carry_t wsum, uint32_t wflag,
                                               typename Op::carry_t *s_wtot, uint32_t *s_wflag,
                                               typename Op::carry_t &wpre, uint32_t &wpref,
                                               typename Op::carry_t &agg, uint32_t &aggf) {
+  static_assert(WAVES <= 64, "one lane per wave");
   if (lane == 0) {
     s_wtot[wave] = wsum;
     s_wflag[wave] = wflag;
   }
   __syncthreads();
+  const int l = lane < WAVES ? lane : 0;
+  const typename Op::carry_t tl = Op::kCombineByLane ? s_wtot[l] : Op::czero();
+  const uint32_t fl = Op::kCombineByLane ? s_wflag[l] : 0u;
   wpre = Op::czero();
   agg = Op::czero();
   wpref = 0u;
@@ -659,8 +677,8 @@ __device__ __forceinline__ void combine_waves(int wave, int lane, typename Op::c
       wpre = agg;
       wpref = aggf;
     }
-    const typename Op::carry_t tw = s_wtot[w];
-    const uint32_t fw = s_wflag[w];
+    const typename Op::carry_t tw = Op::kCombineByLane ? readlane_of(tl, w) : s_wtot[w];
+    const uint32_t fw = Op::kCombineByLane ? readlane32(fl, w) : s_wflag[w];
     agg = fw ? tw : Op::cadd(agg, tw);
     aggf |= fw;
   }
