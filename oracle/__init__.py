@@ -56,6 +56,8 @@ def _load():
         lib.oracle_segmented_op_u32.argtypes = [P, P, P, I64, I, I, I, I]
         lib.oracle_compact_u32.argtypes = [P, P, I64, I, I, ctypes.c_uint32]
         lib.oracle_compact_u32.restype = I64
+        lib.oracle_scan_u64.argtypes = [P, P, I64, I]
+        lib.oracle_scan_u64.restype = None
         for f in (lib.oracle_scan_u32, lib.oracle_scan_f32_f64,
                   lib.oracle_segmented_u32, lib.oracle_segmented_f32_f64,
                   lib.oracle_scan_op_u32, lib.oracle_segmented_op_u32):
@@ -86,6 +88,20 @@ def scan_int(a: np.ndarray, exclusive: bool = False, reverse: bool = False,
     dst = np.empty_like(src) if out is None else _as_u32(out)
     _load().oracle_scan_u32(_ptr(src), _ptr(dst), src.size, int(exclusive), int(reverse))
     return dst.view(np.asarray(a).dtype)
+
+
+def scan_int64(a: np.ndarray, exclusive: bool = False, out: np.ndarray | None = None) -> np.ndarray:
+    """Forward scan of 64-bit integers, wrapping modulo 2^64.
+
+    Returns an array of a's dtype (int64 or uint64); ``out`` may be ``a``.
+    """
+    a = np.ascontiguousarray(a)
+    if a.dtype not in (np.uint64, np.int64):
+        raise TypeError("64-bit oracle takes int64/uint64, got %s" % a.dtype)
+    src = a.view(np.uint64)
+    dst = np.empty_like(src) if out is None else out.view(np.uint64)
+    _load().oracle_scan_u64(_ptr(src), _ptr(dst), src.size, int(exclusive))
+    return dst.view(a.dtype)
 
 
 def scan_f32(a: np.ndarray, exclusive: bool = False, reverse: bool = False,

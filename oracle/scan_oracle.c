@@ -17,7 +17,7 @@
  *
  * Integer element types add in uint32_t, i.e. modulo 2^32 (the paper is silent
  * on overflow; wrap-around is the reading taken).  32-bit signed data is the
- * same bit pattern.  Float32 inputs are accumulated in float64 (the paper
+ * same bit pattern.  64-bit integers likewise add in uint64_t, modulo 2^64.  Float32 inputs are accumulated in float64 (the paper
  * notes that parallel float results may differ from the sequential ones; the
  * oracle therefore computes the sequential sum in a wider type and also
  * returns the running sum of absolute values, which sets the tolerance).
@@ -111,6 +111,18 @@ void oracle_scan_u32(const uint32_t *a, uint32_t *out, int64_t n,
             if (exclusive) { out[i] = acc; acc += x; }
             else           { acc += x; out[i] = acc; }
         }
+    }
+}
+
+/* 64-bit integers: the same pass in uint64_t, modulo 2^64 (int64 data is the
+ * same bit pattern).  Forward only. */
+void oracle_scan_u64(const uint64_t *a, uint64_t *out, int64_t n, int exclusive)
+{
+    uint64_t acc = 0u;
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t x = a[i];
+        if (exclusive) { out[i] = acc; acc += x; }
+        else           { acc += x; out[i] = acc; }
     }
 }
 

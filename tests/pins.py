@@ -116,6 +116,65 @@ def pin_int_flat(scan_int) -> list:
     return fails
 
 
+M64 = 1 << 64
+
+
+def _cmp64(name, got, want, fails):
+    got = [int(x) for x in np.asarray(got).view(np.uint64)]
+    want = [int(x) % M64 for x in want]
+    if got != want:
+        bad = next(i for i, (g, w) in enumerate(zip(got, want)) if g != w) if len(got) == len(want) else -1
+        fails.append("%s: mismatch (first at %d)" % (name, bad))
+
+
+def pin_int64(scan64) -> list:
+    """scan64(a, exclusive) -> array: forward scan wrapping modulo 2^64."""
+    fails = []
+    g = golden_io.load("wrap_u64.txt")
+    a = np.array(g["input"], dtype=np.uint64)
+    _cmp64("golden inclusive", scan64(a, False), g["inclusive"], fails)
+    _cmp64("golden exclusive", scan64(a, True), g["exclusive"], fails)
+
+    # closed form: a_i = c + d*i (mod 2^64) -> (i+1)c + d*i(i+1)/2, with values
+    # that carry out of the low 32 bits at every step and wrap past 2^64
+    c, d = 0xFFFFFFFF, 0x9E3779B97F4A7C15
+    n = 20000
+    a = np.array([(c + d * k) % M64 for k in range(n)], dtype=np.uint64)
+    want = [((k + 1) * c + d * k * (k + 1) // 2) % M64 for k in range(n)]
+    _cmp64("arithmetic progression inclusive", scan64(a, False), want, fails)
+    want_ex = [(k * c + d * (k - 1) * k // 2) % M64 for k in range(n)]
+    _cmp64("arithmetic progression exclusive", scan64(a, True), want_ex, fails)
+
+    # brute force from the definition in Python integers
+    rng = np.random.default_rng(11)
+    for n in (0, 1, 2, 3, 17, 64, 65, 257):
+        a = rng.integers(0, M64, size=n, dtype=np.uint64)
+        v = [int(x) for x in a]
+        for ex in (False, True):
+            want = [sum(v[:i] if ex else v[:i + 1]) for i in range(n)]
+            _cmp64("brute n=%d ex=%d" % (n, ex), scan64(a, ex), want, fails)
+
+    # numpy's wrapping uint64 cumsum
+    a = rng.integers(0, M64, size=100_003, dtype=np.uint64)
+    inc = np.asarray(scan64(a, False)).view(np.uint64)
+    exc = np.asarray(scan64(a, True)).view(np.uint64)
+    if not np.array_equal(inc, np.cumsum(a, dtype=np.uint64)):
+        fails.append("numpy cumsum uint64")
+    # invariants: inclusive - exclusive = input; the low 32 bits are the
+    # 32-bit scan of the low halves
+    if not np.array_equal(inc - exc, a):
+        fails.append("inclusive - exclusive != input")
+    lo = (a & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    if not np.array_equal((inc & np.uint64(0xFFFFFFFF)).astype(np.uint32), np.cumsum(lo, dtype=np.uint32)):
+        fails.append("low halves differ from the 32-bit scan")
+    # signed view: negative int64 input, the same bits as uint64
+    neg = -np.arange(1, 1001, dtype=np.int64)
+    s = np.asarray(scan64(neg, False))
+    if s.dtype != np.int64 or [int(x) for x in s] != [-(k + 1) * (k + 2) // 2 for k in range(1000)]:
+        fails.append("int64 negative input")
+    return fails
+
+
 def pin_int_inplace(scan_int_out) -> list:
     """scan_int_out(a, exclusive, reverse, out) with out == a."""
     fails = []

@@ -218,3 +218,47 @@ def _m_op_reverse_ignored(a, op, ex, rev):
                                     _m_op_or_for_xor, _m_op_reverse_ignored])
 def test_pins_catch_operator_mutant(mutant):
     assert pins.pin_int_operators(mutant) != []
+
+
+# ---------------------------------------------------------------- 64-bit integers
+
+def test_oracle_int64_pinned():
+    assert pins.pin_int64(lambda a, ex: oracle.scan_int64(a, exclusive=ex)) == []
+
+
+def _m64_split_halves(a, ex):
+    # scans the two 32-bit halves separately: the carry out of the low half is lost
+    v = np.ascontiguousarray(a).view(np.uint64)
+    lo = np.asarray(oracle.scan_int((v & np.uint64(0xFFFFFFFF)).astype(np.uint32), exclusive=ex)).astype(np.uint64)
+    hi = np.asarray(oracle.scan_int((v >> np.uint64(32)).astype(np.uint32), exclusive=ex)).astype(np.uint64)
+    return ((hi << np.uint64(32)) | lo).view(np.asarray(a).dtype)
+
+
+def _m64_float_accumulator(a, ex):
+    v = np.ascontiguousarray(a).view(np.uint64).astype(np.float64)
+    c = np.cumsum(v) - (v if ex else 0)
+    return np.mod(c, 2.0**64).astype(np.uint64).view(np.asarray(a).dtype)
+
+
+def _m64_exclusive_is_inclusive(a, ex):
+    return oracle.scan_int64(a, exclusive=False)
+
+
+def _m64_no_wrap_signed(a, ex):
+    # accumulates in signed 64 bits saturating at the int64 range
+    v = [int(x) for x in np.ascontiguousarray(a).view(np.int64)]
+    out, acc = [], 0
+    for x in v:
+        if ex:
+            out.append(acc)
+            acc = max(min(acc + x, 2**63 - 1), -2**63)
+        else:
+            acc = max(min(acc + x, 2**63 - 1), -2**63)
+            out.append(acc)
+    return np.array(out, dtype=np.int64).view(np.asarray(a).dtype)
+
+
+@pytest.mark.parametrize("mutant", [_m64_split_halves, _m64_float_accumulator, _m64_exclusive_is_inclusive,
+                                    _m64_no_wrap_signed])
+def test_pins_catch_int64_mutant(mutant):
+    assert pins.pin_int64(mutant) != []
