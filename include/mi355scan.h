@@ -65,7 +65,9 @@ typedef enum {
     SCAN_ERROR_TIMEOUT = 7          /* a device-side wait hit its spin limit */
 } scan_status_t;
 
-typedef enum { SCAN_I32 = 0, SCAN_U32 = 1, SCAN_F32 = 2 } scan_dtype_t;
+/* SCAN_I64 / SCAN_U64: 64-bit integer sums (wrapping modulo 2^64, the same
+ * bits for both), scan_flat only: see scan_flat. */
+typedef enum { SCAN_I32 = 0, SCAN_U32 = 1, SCAN_F32 = 2, SCAN_I64 = 3, SCAN_U64 = 4 } scan_dtype_t;
 
 /* Flag bits. */
 #define SCAN_EXCLUSIVE 0x1u  /* exclusive scan (identity first)              */
@@ -95,7 +97,13 @@ scan_status_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, h
 scan_status_t scan_exclusive_f32(const float *in, float *out, int64_t n, hipStream_t stream);
 
 /* General flat scan: any dtype, flags = SCAN_EXCLUSIVE | SCAN_REVERSE, plus
- * an operator (SCAN_OP_*) for i32 / u32. */
+ * an operator (SCAN_OP_*) for i32 / u32.
+ * SCAN_I64 / SCAN_U64 (the Introduction's scan with + on 64-bit integers,
+ * e.g. offsets past 2^32): in and out must be 16-byte aligned
+ * (SCAN_ERROR_INVALID_VALUE otherwise), flags SCAN_EXCLUSIVE only (SCAN_REVERSE
+ * or an operator: SCAN_ERROR_NOT_SUPPORTED); bit-exact, wrapping modulo 2^64.
+ * The other entry points return SCAN_ERROR_NOT_SUPPORTED for these dtypes.
+ * Uses the stream's workspace (two status words per 32768-element tile). */
 scan_status_t scan_flat(const void *in, void *out, int64_t n, scan_dtype_t dtype,
                         uint32_t flags, hipStream_t stream);
 

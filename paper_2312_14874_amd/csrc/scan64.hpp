@@ -1,0 +1,251 @@
+// Single-pass scans of 64-bit integers (wrapping modulo 2^64; int64 and
+// uint64 are the same bits): the same decoupled look-back as the 32-bit
+// kernel, with a tile's status held in two 64-bit words.  Each word carries
+// the 2-bit flag and one 32-bit half of the value and is moved by a single
+// relaxed atomic access; a reader takes the pair only when both halves carry
+// the same flag (flags only move forward, EMPTY -> AGG -> PREFIX, so a pair
+// with different flags is a publication in progress and reads as EMPTY), so
+// no fences are needed.  A lane holds two elements per 16-byte load; a
+// chunk is 128 elements.  Flat forward scans, inclusive or exclusive.
+#pragma once
+#include "scan_device.hpp"
+
+namespace mi355scan {
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint64_t dpp64(uint64_t x) {
+  const uint32_t lo = dpp<CTRL, ROW_MASK>((uint32_t)x);
+  const uint32_t hi = dpp<CTRL, ROW_MASK>((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive wave scan of 64-bit integers (the 32-bit wave_scan's steps on
+// both halves, then a 64-bit add).
+__device__ __forceinline__ uint64_t wave_scan64(uint64_t x) {
+  x += dpp64<0x111, 0xf>(x);
+  x += dpp64<0x112, 0xf>(x);
+  x += dpp64<0x114, 0xf>(x);
+  x += dpp64<0x118, 0xf>(x);
+  x += dpp64<0x142, 0xa>(x);
+  x += dpp64<0x143, 0xc>(x);
+  return x;
+}
+
+__device__ __forceinline__ uint64_t lane_up1_64(uint64_t x) { return dpp64<0x138, 0xf>(x); }
+
+// Status pair of tile t: words 2t (low half) and 2t+1 (high half).
+__device__ __forceinline__ void publish64(uint64_t *st, int64_t t, uint64_t v, uint32_t flag) {
+  st_agent(st + 2 * t, ((uint64_t)flag << 32) | (uint32_t)v);
+  st_agent(st + 2 * t + 1, ((uint64_t)flag << 32) | (uint32_t)(v >> 32));
+}
+
+// Take the next tile (one wave, uniform result): as acquire_tile, with two
+// status words per tile to clear in the other array and 2*tiles words used.
+__device__ __forceinline__ void hand_over64(const KernelArgs &a, uint32_t p, uint64_t clear_hi, int nthreads) {
+  uint64_t *other = a.status + (1 - p) * a.capacity;
+  const uint32_t me = opaque_tid() % (uint32_t)nthreads;
+  for (uint64_t i = 2 * (uint64_t)a.tiles + me; i < clear_hi; i += nthreads) st_agent(other + i, 0ull);
+  if (me == 0) {
+    st_agent(&a.hdr->counter[1 - p], 0ull);
+    st_agent(&a.hdr->dirty[1 - p], 0ull);
+    st_agent(&a.hdr->dirty[p], 2 * (uint64_t)a.tiles);
+    st_agent32(&a.hdr->parity, 1u - p);
+  }
+}
+
+__device__ __forceinline__ int64_t acquire_tile64(const KernelArgs &a, uint32_t parity, int lane) {
+  uint64_t tk = 0, clear_hi = 0;
+  uint32_t last = 0;
+  if (lane == 0) {
+    tk = __hip_atomic_fetch_add(&a.hdr->counter[parity], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    last = tk == a.total_acquires - 1;
+    if (tk < (uint64_t)a.tiles) {
+      st_agent(a.status + (1 - parity) * a.capacity + 2 * tk, 0ull);
+      st_agent(a.status + (1 - parity) * a.capacity + 2 * tk + 1, 0ull);
+    }
+    if (last) clear_hi = ld_agent(&a.hdr->dirty[1 - parity]);
+  }
+  tk = readlane64(tk, 0);
+  if (readlane32(last, 0)) hand_over64(a, parity, readlane64(clear_hi, 0), 64);
+  return (int64_t)tk;
+}
+
+// Carry into tile t (one wave): sum of the aggregates back to the nearest
+// PREFIX, read 64 tiles per poll (lane l: tile t-1-l of the window).
+__device__ uint64_t look_back64(const uint64_t *st, int64_t t, uint32_t spin_limit, WsHeader *hdr) {
+  const int lane = (int)(opaque_tid() & 63u);
+  uint64_t acc = 0;
+  int64_t base = t - 1;
+  for (uint32_t spins = 0;;) {
+    const int64_t idx = base - lane;
+    uint64_t lo = ((uint64_t)kPrefix << 32), hi = ((uint64_t)kPrefix << 32);   // before tile 0: empty PREFIX
+    if (idx >= 0) {
+      lo = ld_agent(st + 2 * idx);
+      hi = ld_agent(st + 2 * idx + 1);
+    }
+    const uint32_t flo = (uint32_t)(lo >> 32), fhi = (uint32_t)(hi >> 32);
+    const uint32_t f = flo == fhi ? flo : kEmpty;
+    const uint64_t v = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+    const uint64_t bP = ballot(f == kPrefix), bE = ballot(f == kEmpty);
+    const int dP = bP ? __builtin_ctzll(bP) : 64, dE = bE ? __builtin_ctzll(bE) : 64;
+    if (dE < dP) {
+      if (++spins > spin_limit) {
+        if (lane == 0) st_agent32(&hdr->error, 1u);
+        return acc;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    // lanes 0..min(dP, 63) hold aggregates (and the PREFIX at dP)
+    const uint64_t part = readlane64(wave_scan64(lane <= dP ? v : 0ull), 63);
+    acc += part;
+    if (dP < 64) return acc;
+    base -= 64;
+  }
+}
+
+// One wave's span of tile t in an 8-byte-element buffer: 16-byte loads and
+// stores, lane l of chunk c at byte 1024c + 16l; the buffer resource's
+// record count returns 0 beyond n and drops stores there.
+template <int WSPAN>
+struct WaveSpan64 {
+  __amdgpu_buffer_rsrc_t rs;
+  uint32_t lo;
+  __device__ __forceinline__ WaveSpan64(const void *buf, int64_t n, int64_t wb) {
+    const int64_t valid = (n - wb) * 8;
+    const int nr = valid <= 0 ? 0 : (valid >= 8 * WSPAN ? 8 * WSPAN : (int)valid);
+    rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint64_t *>(static_cast<const uint64_t *>(buf)) + wb,
+                                           (short)0, nr, 0x00020000);
+    lo = 16u * (opaque_tid() & 63u);
+  }
+  __device__ __forceinline__ void load(int c, u32x4 &r) const {
+    r = __builtin_amdgcn_raw_buffer_load_b128(rs, lo + 1024u * (uint32_t)c, 0, kNtAux);
+  }
+  __device__ __forceinline__ void store(int c, const u32x4 &r) const {
+    __builtin_amdgcn_raw_buffer_store_b128(r, rs, lo + 1024u * (uint32_t)c, 0, kNtAux);
+  }
+};
+
+__device__ __forceinline__ uint64_t u64_of(uint32_t lo, uint32_t hi) { return ((uint64_t)hi << 32) | lo; }
+
+// Resident grid, tiles from the device counter; ITEMS elements per thread
+// (2 per chunk and lane), the wave's span WSPAN = 64 * ITEMS elements.
+template <int BLOCK, int ITEMS, int MINW>
+__global__ void __launch_bounds__(BLOCK, MINW) scan64_tiles(KernelArgs a) {
+  static_assert(ITEMS % 2 == 0, "two elements per 16-byte group");
+  constexpr int WAVES = BLOCK / 64;
+  constexpr int CH = ITEMS / 2;
+  constexpr int WSPAN = 64 * ITEMS;
+  constexpr int64_t TILE = (int64_t)BLOCK * ITEMS;
+  __shared__ uint64_t s_wtot[WAVES];
+  __shared__ uint64_t s_carry;
+  __shared__ int64_t s_tile;
+  __shared__ uint32_t s_parity;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = wave_id();
+  const bool multi = a.tiles > 1;
+  const bool ex = a.exclusive != 0u;
+  uint32_t parity = 0;
+  int64_t t = 0;
+  if (multi) {
+    if (wave == 0) {
+      parity = readlane32(lane == 0 ? ld_agent32(&a.hdr->parity) : 0u, 0);
+      t = acquire_tile64(a, parity, lane);
+      if (lane == 0) {
+        s_parity = parity;
+        s_tile = t;
+      }
+    }
+    __syncthreads();
+    parity = s_parity;
+    t = s_tile;
+  }
+  u32x4 R[CH];
+  if (t < a.tiles) {
+    const WaveSpan64<WSPAN> in(a.in, a.n, t * TILE + (int64_t)wave * WSPAN);
+#pragma unroll
+    for (int c = 0; c < CH; ++c) in.load(c, R[c]);
+  }
+  while (t < a.tiles) {
+    // in-register scan: per chunk the lane's two elements, then the lanes
+    uint64_t wsum = 0;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const uint64_t x0 = u64_of(R[c][0], R[c][1]);
+      const uint64_t x1 = u64_of(R[c][2], R[c][3]) + x0;
+      const uint64_t x = wave_scan64(x1);
+      const uint64_t off = lane_up1_64(x) + (c > 0 ? wsum : 0ull);
+      const uint64_t o0 = ex ? off : off + x0;
+      const uint64_t o1 = ex ? off + x0 : off + x1;
+      R[c][0] = (uint32_t)o0;
+      R[c][1] = (uint32_t)(o0 >> 32);
+      R[c][2] = (uint32_t)o1;
+      R[c][3] = (uint32_t)(o1 >> 32);
+      wsum += readlane64(x, 63);
+      asm volatile("" : "+v"(R[c]));
+    }
+    // wave totals: this wave's prefix and the tile's aggregate, left to right
+    if (lane == 0) s_wtot[wave] = wsum;
+    __syncthreads();
+    uint64_t wpre = 0, agg = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+      if (w == wave) wpre = agg;
+      agg += s_wtot[w];
+    }
+    if (multi && wave == 0) {
+      uint64_t *st = a.status + parity * a.capacity;
+      uint64_t carry = 0;
+      if (t == 0) {
+        if (lane == 0) publish64(st, t, agg, kPrefix);
+      } else {
+        if (lane == 0) publish64(st, t, agg, kAgg);
+        carry = look_back64(st, t, a.spin_limit, a.hdr);
+        if (lane == 0) publish64(st, t, carry + agg, kPrefix);
+      }
+      if (lane == 0) s_carry = carry;
+    }
+    __syncthreads();
+    const uint64_t win = (t > 0 ? s_carry : 0ull) + wpre;
+    const WaveSpan64<WSPAN> out(a.out, a.n, t * TILE + (int64_t)wave * WSPAN);
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const uint64_t o0 = u64_of(R[c][0], R[c][1]) + win, o1 = u64_of(R[c][2], R[c][3]) + win;
+      R[c][0] = (uint32_t)o0;
+      R[c][1] = (uint32_t)(o0 >> 32);
+      R[c][2] = (uint32_t)o1;
+      R[c][3] = (uint32_t)(o1 >> 32);
+    }
+    // store, taking the next tile after the first half, and load it into the
+    // registers each further store frees (as scan_tiles does)
+    constexpr int KH = CH / 2;
+#pragma unroll
+    for (int c = 0; c < KH; ++c) out.store(c, R[c]);
+    int64_t next = a.tiles;
+    if (multi) {
+      if (wave == 0) {
+        const int64_t tk = acquire_tile64(a, parity, lane);
+        if (lane == 0) s_tile = tk;
+      }
+      __syncthreads();
+      next = s_tile;
+    }
+    if (next < a.tiles) {
+      const WaveSpan64<WSPAN> in(a.in, a.n, next * TILE + (int64_t)wave * WSPAN);
+#pragma unroll
+      for (int c = KH; c < CH; ++c) {
+        out.store(c, R[c]);
+        in.load(c - KH, R[c - KH]);
+      }
+#pragma unroll
+      for (int c = CH - KH; c < CH; ++c) in.load(c, R[c]);
+    } else {
+#pragma unroll
+      for (int c = KH; c < CH; ++c) out.store(c, R[c]);
+    }
+    t = next;
+  }
+}
+
+}  // namespace mi355scan

@@ -1,0 +1,12 @@
+// Instantiation of the 64-bit integer scan kernel for gfx950.
+#include "scan64.hpp"
+#include "scan_table.hpp"
+
+namespace mi355scan {
+
+// 512 threads x 64 elements per tile (two per 16-byte group), one resident
+// workgroup per CU
+const void *kScan64 = (const void *)&scan64_tiles<512, 64, 2>;
+const int kScan64Block = 512, kScan64Items = 64;
+
+}  // namespace mi355scan

@@ -348,8 +348,52 @@ scan_status_t launch(const Call &c, hipStream_t stream, Workspace *ws_override, 
   return SCAN_SUCCESS;
 }
 
+// 64-bit integer scans: one resident launch of the 64-bit kernel over
+// 32768-element tiles (tiles from the counter), two status words per tile.
+scan_status_t flat64(const void *in, void *out, int64_t n, uint32_t flags, hipStream_t stream) {
+  int r = check_flags(flags);
+  if (r == kOk) r = check_flat_sz(in, out, n, 8);
+  if (r != kOk) return st(r);
+  if (flags & ~(uint32_t)SCAN_EXCLUSIVE) return SCAN_ERROR_NOT_SUPPORTED;   // forward +-scans only
+  if (((uintptr_t)in & 15u) || ((uintptr_t)out & 15u)) return SCAN_ERROR_INVALID_VALUE;
+  if (n == 0) return SCAN_SUCCESS;
+  ensure_init();
+  int dev = 0;
+  DeviceInfo di;
+  scan_status_t s = current_device(&dev, &di);
+  if (s != SCAN_SUCCESS) return s;
+  const int64_t tile = (int64_t)kScan64Block * kScan64Items;
+  const int64_t T = tiles_for(n, tile);
+  if (2 * T > kMaxTiles) return SCAN_ERROR_NOT_SUPPORTED;
+  Workspace *ws = nullptr;
+  if (T > 1) {
+    s = stream_ws(dev, stream, 2 * T, &ws);
+    if (s != SCAN_SUCCESS) return s;
+  }
+  const int64_t grid = std::min<int64_t>(T, resident_grid(kScan64, kScan64Block, di.cus, 0, 100));
+  KernelArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.in = in;
+  a.out = out;
+  a.n = n;
+  a.tiles = T;
+  a.hdr = ws ? ws->hdr : nullptr;
+  a.status = ws ? ws->status : nullptr;
+  a.capacity = ws ? ws->capacity : 0;
+  a.total_acquires = (uint64_t)(T + grid);   // every workgroup also takes one tile past the end
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    a.spin_limit = g_spin_limit;
+  }
+  a.exclusive = (flags & SCAN_EXCLUSIVE) ? 1u : 0u;
+  void *args[] = {&a};
+  hipError_t e = hipLaunchKernel(kScan64, dim3((unsigned)grid), dim3(kScan64Block), args, 0, stream);
+  return e == hipSuccess ? SCAN_SUCCESS : hip_fail(e);
+}
+
 scan_status_t flat(const void *in, void *out, int64_t n, scan_dtype_t dt, uint32_t flags,
                    hipStream_t stream) {
+  if (is_dtype64((int)dt)) return flat64(in, out, n, flags, stream);
   int r = check_dtype((int)dt);
   if (r == kOk) r = check_flags(flags);
   if (r == kOk) r = check_flat(in, out, n);

@@ -930,22 +930,4 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
   if (multi && a.stride) static_done(a, parity, tid, BLOCK, &s_flag, &s_clear_hi);
 }
 
-// For each tile boundary p in [0, T]: the first segment index s with
-// offsets[s] >= p*TILE + shift (shift 1 for reverse scans, where a segment's
-// first logical element is its last physical one).  Plain binary search over
-// the S+1 offsets; never reads outside offsets[0..S].
-__global__ void tile_segment_map(const int64_t *offsets, int64_t num_segments, int64_t tile,
-                                 int64_t tiles, int32_t shift, uint32_t *map) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p > tiles) return;
-  const int64_t x = p * tile + shift;
-  int64_t lo = 0, hi = num_segments + 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (offsets[mid] < x) lo = mid + 1;
-    else hi = mid;
-  }
-  map[p] = (uint32_t)lo;
-}
-
 }  // namespace mi355scan

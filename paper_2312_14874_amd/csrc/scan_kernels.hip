@@ -69,6 +69,24 @@ const Config kConfigs[] = {
 };
 const int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
+// For each tile boundary p in [0, T]: the first segment index s with
+// offsets[s] >= p*TILE + shift (shift 1 for reverse scans, where a segment's
+// first logical element is its last physical one).  Plain binary search over
+// the S+1 offsets; never reads outside offsets[0..S].
+__global__ void tile_segment_map(const int64_t *offsets, int64_t num_segments, int64_t tile,
+                                 int64_t tiles, int32_t shift, uint32_t *map) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > tiles) return;
+  const int64_t x = p * tile + shift;
+  int64_t lo = 0, hi = num_segments + 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (offsets[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  map[p] = (uint32_t)lo;
+}
+
 const void *kTileSegmentMap = (const void *)&tile_segment_map;
 
 // two-pass kernels: 256 threads x 64 elements (16384-element tiles); the

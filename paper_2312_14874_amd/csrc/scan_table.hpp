@@ -55,4 +55,8 @@ struct CompactKernels {
 };
 extern const CompactKernels kCompact;
 
+// 64-bit integer scans (flat, forward, 16-byte aligned buffers).
+extern const void *kScan64;
+extern const int kScan64Block, kScan64Items;
+
 }  // namespace mi355scan

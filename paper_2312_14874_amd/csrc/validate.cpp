@@ -2,7 +2,10 @@
 
 namespace mi355scan {
 
-int check_dtype(int dtype) { return (dtype >= 0 && dtype <= 2) ? kOk : kInvalid; }
+int check_dtype(int dtype) {
+  if (dtype >= 0 && dtype <= 2) return kOk;
+  return is_dtype64(dtype) ? kNotSupported : kInvalid;   // 64-bit: scan_flat only
+}
 
 int check_flags(uint32_t flags) { return (flags & ~kKnownFlags) ? kInvalid : kOk; }
 
@@ -31,14 +34,16 @@ int check_operator(int dtype, uint32_t flags) {
   return kOk;
 }
 
-int check_flat(const void *in, const void *out, int64_t n) {
+int check_flat(const void *in, const void *out, int64_t n) { return check_flat_sz(in, out, n, 4); }
+
+int check_flat_sz(const void *in, const void *out, int64_t n, int esize) {
   if (n < 0) return kInvalid;
   if (n == 0) return kOk;
   if (!in || !out) return kInvalid;
   const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
-  if ((a & 3u) || (b & 3u)) return kInvalid;
-  if (n > (int64_t)(UINTPTR_MAX / 8)) return kInvalid;
-  const uintptr_t bytes = (uintptr_t)n * 4u;
+  if ((a % (uintptr_t)esize) || (b % (uintptr_t)esize)) return kInvalid;
+  if (n > (int64_t)(UINTPTR_MAX / 16)) return kInvalid;
+  const uintptr_t bytes = (uintptr_t)n * (uintptr_t)esize;
   if (a + bytes < a || b + bytes < b) return kInvalid;   // address wrap
   if (a != b && a < b + bytes && b < a + bytes) return kOverlap;
   return kOk;

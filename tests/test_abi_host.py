@@ -44,7 +44,7 @@ INVALID, OVERLAP = 1, 2
 @pytest.mark.parametrize("args,code", [
     ((None, None, 10, 0, 0), INVALID),          # null pointers
     ((4096, 8192, -1, 0, 0), INVALID),          # n < 0
-    ((4096, 8192, 10, 3, 0), INVALID),          # unknown dtype
+    ((4096, 8192, 10, 7, 0), INVALID),          # unknown dtype
     ((4096, 8192, 10, 0, 0x10), INVALID),       # unknown flag
     ((4098, 8192, 10, 0, 0), INVALID),          # misaligned (needs 4 bytes)
     ((4096, 4100, 10, 0, 0), OVERLAP),          # partial overlap
@@ -103,7 +103,7 @@ def test_compact_argument_errors():
     assert f(4096, 8192, 10, 0, 2, 0, 16, None) == INVALID          # unknown predicate
     assert f(None, None, 10, 0, 0, 0, 16, None) == INVALID          # null pointers
     assert f(4096, 4100, 10, 0, 0, 0, 16, None) == OVERLAP
-    assert f(4096, 8192, 10, 3, 0, 0, 16, None) == INVALID          # unknown dtype
+    assert f(4096, 8192, 10, 7, 0, 0, 16, None) == INVALID          # unknown dtype
     assert f(1 << 40, 1 << 41, 1 << 33, 0, 0, 0, 16, None) == NOT_SUPPORTED   # n >= 2^32
 
 
@@ -114,9 +114,29 @@ def test_two_pass_argument_errors():
     assert f(None, None, 10, 0, 0, 0, 0, None) == INVALID           # null pointers
     assert f(4096, 8192, 10, 0, 0, 2, 0, None) == INVALID           # unknown method
     assert f(4096, 8192, 10, 0, 0, 1, -1, None) == INVALID          # partition < 0
-    assert f(4096, 8192, 10, 3, 0, 1, 0, None) == INVALID           # unknown dtype
+    assert f(4096, 8192, 10, 7, 0, 1, 0, None) == INVALID           # unknown dtype
     assert f(4096, 4100, 10, 0, 0, 1, 0, None) == OVERLAP
     assert f(4096, 8192, 10, 0, 2, 1, 0, None) == 5                 # reverse: not supported
+
+
+I64, U64 = 3, 4
+
+
+def test_int64_argument_errors():
+    L = _lib()
+    f = L.lib.scan_flat
+    assert f(None, None, 0, I64, 0, None) == 0                      # n = 0: no-op
+    assert f(None, None, 10, I64, 0, None) == INVALID               # null pointers
+    assert f(4100, 8192, 10, U64, 0, None) == INVALID               # not 8-byte aligned
+    assert f(4104, 8192, 10, I64, 0, None) == INVALID               # 8- but not 16-byte aligned
+    assert f(4096, 4136, 10, I64, 0, None) == OVERLAP               # 8-byte elements overlap
+    assert f(4096, 8192, 10, I64, REV, None) == NOT_SUPPORTED       # forward only
+    assert f(4096, 8192, 10, U64, OP_MAX, None) == NOT_SUPPORTED    # + only
+    assert f(4096, 8192, 10, I64, 0x10, None) == INVALID            # unknown flag
+    # the other entry points take 32-bit dtypes only
+    assert L.lib.scan_segmented_batch(4096, 8192, 16, 1, 10, I64, 0, None) == NOT_SUPPORTED
+    assert L.lib.scan_two_pass(4096, 8192, 10, U64, 0, 1, 0, None) == NOT_SUPPORTED
+    assert L.lib.scan_compact(4096, 8192, 10, I64, 0, 0, 16, None) == NOT_SUPPORTED
 
 
 def test_other_argument_errors():

@@ -1,0 +1,101 @@
+"""64-bit integer scans (scan_flat with SCAN_I64 / SCAN_U64) against the
+oracle, bit-exact: ragged sizes across tile boundaries, inclusive and
+exclusive, in place, carries out of the low 32 bits, wrap-around modulo 2^64,
+a workspace shared with 32-bit scans on one stream, and 2^28 elements."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import check_status, first_mismatch, flat, lib, stream
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+I64, U64 = 3, 4
+TILE = 512 * 64   # elements per tile of the 64-bit kernel
+
+
+def to_dev64(a: np.ndarray, pad: int = 2) -> torch.Tensor:
+    """int64 device copy with `pad` spare elements in front (2 keeps 16-byte alignment)."""
+    t = torch.empty(a.size + pad, dtype=torch.int64, device="cuda")
+    t[pad:].copy_(torch.from_numpy(np.ascontiguousarray(a).view(np.int64)))
+    return t[pad:]
+
+
+def run64(a: np.ndarray, exclusive=False, inplace=False) -> np.ndarray:
+    x = to_dev64(a)
+    out = x if inplace else to_dev64(np.zeros(a.size, dtype=np.int64))
+    dt = U64 if a.dtype == np.uint64 else I64
+    check_status(lib().scan_flat(x.data_ptr(), out.data_ptr(), a.size, dt, 1 if exclusive else 0, stream()),
+                 "scan_flat n=%d" % a.size)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(a.dtype)
+
+
+def data(n, seed, dtype=np.uint64, kind="uniform"):
+    g = np.random.default_rng(seed)
+    if kind == "uniform":        # the whole 64-bit range: wraps at almost every step
+        a = g.integers(0, 1 << 64, size=n, dtype=np.uint64)
+    elif kind == "carry":        # low halves near 2^32: a carry into the high half at most steps
+        a = (np.uint64(0xFFFFFFFF) - g.integers(0, 16, size=n, dtype=np.uint64))
+    else:                        # small signed values: sums stay near zero
+        a = g.integers(-1000, 1000, size=n, dtype=np.int64).view(np.uint64)
+    return a.view(dtype)
+
+
+def check(a, exclusive=False, **kw):
+    want = oracle.scan_int64(a, exclusive=exclusive)
+    got = run64(a, exclusive, **kw)
+    assert got.dtype == a.dtype
+    err = first_mismatch(got.view(np.uint64), want.view(np.uint64))
+    assert not err, "n=%d ex=%d: %s" % (a.size, exclusive, err)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 127, 128, 129, TILE - 1, TILE, TILE + 1, 5 * TILE + 777, (1 << 20) + 3])
+@pytest.mark.parametrize("exclusive", [False, True])
+def test_ragged(n, exclusive):
+    check(data(n, 6000 + n % 97), exclusive)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "carry", "small"])
+@pytest.mark.parametrize("dtype", [np.int64, np.uint64])
+def test_value_patterns(kind, dtype):
+    check(data(37 * TILE + 4099, 6100, dtype, kind), exclusive=False)
+    check(data(37 * TILE + 4099, 6101, dtype, kind), exclusive=True)
+
+
+def test_in_place():
+    check(data(11 * TILE + 5, 6200), inplace=True)
+    check(data(11 * TILE + 5, 6201), exclusive=True, inplace=True)
+
+
+def test_shares_workspace_with_32bit_scans():
+    # the stream's status words alternate between the two protocols (one word
+    # per 32-bit tile, two per 64-bit tile) and between large and small calls
+    g = np.random.default_rng(6300)
+    for step, (bits, n) in enumerate([(32, 1 << 26), (64, 1 << 22), (32, 1 << 26), (64, 1 << 26),
+                                      (32, 1 << 20), (64, 3 * TILE + 1), (64, 1 << 25), (32, 1 << 24)]):
+        if bits == 32:
+            a = g.integers(0, 1 << 32, size=n, dtype=np.uint32)
+            err = first_mismatch(flat(a), np.asarray(oracle.scan_int(a)))
+        else:
+            a = data(n, 6400 + step)
+            err = first_mismatch(run64(a), oracle.scan_int64(a))
+        assert not err, "step %d (%d-bit, n=%d): %s" % (step, bits, n, err)
+
+
+def test_torch_binding():
+    import paper_2312_14874_amd as m
+    a = data(3 * TILE + 17, 6500, np.int64, "small")
+    x = torch.from_numpy(a).cuda()
+    assert x.data_ptr() % 16 == 0
+    got = m.cumsum(x).cpu().numpy()
+    assert not first_mismatch(got, oracle.scan_int64(a))
+    got = m.cumsum(x, exclusive=True).cpu().numpy()
+    assert not first_mismatch(got, oracle.scan_int64(a, exclusive=True))
+    with pytest.raises(m.ScanError):
+        m.cumsum(x, reverse=True)
+
+
+def test_full_size():
+    check(data(1 << 28, 6600), exclusive=False)
