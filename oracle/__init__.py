@@ -58,6 +58,8 @@ def _load():
         lib.oracle_compact_u32.restype = I64
         lib.oracle_scan_u64.argtypes = [P, P, I64, I]
         lib.oracle_scan_u64.restype = None
+        lib.oracle_scan_f64.argtypes = [P, P, P, I64, I]
+        lib.oracle_scan_f64.restype = None
         for f in (lib.oracle_scan_u32, lib.oracle_scan_f32_f64,
                   lib.oracle_segmented_u32, lib.oracle_segmented_f32_f64,
                   lib.oracle_scan_op_u32, lib.oracle_segmented_op_u32):
@@ -102,6 +104,27 @@ def scan_int64(a: np.ndarray, exclusive: bool = False, out: np.ndarray | None = 
     dst = np.empty_like(src) if out is None else out.view(np.uint64)
     _load().oracle_scan_u64(_ptr(src), _ptr(dst), src.size, int(exclusive))
     return dst.view(a.dtype)
+
+
+def scan_f64(a: np.ndarray, exclusive: bool = False, with_abs: bool = True):
+    """Forward prefix sums of float64 input, accumulated in double-double and
+    rounded once to float64.
+
+    Returns (sums, abs_sums): float64 arrays; abs_sums[i] is the running sum
+    of |a| (the scale of the error tolerance), or None if ``with_abs`` is False.
+    """
+    src = np.ascontiguousarray(a, dtype=np.float64)
+    s = np.empty(src.size, dtype=np.float64)
+    ab = np.empty(src.size, dtype=np.float64) if with_abs else None
+    _load().oracle_scan_f64(_ptr(src), _ptr(s), _ptr(ab), src.size, int(exclusive))
+    return s, ab
+
+
+def f64_tolerance(abs_sums: np.ndarray, depth: int) -> np.ndarray:
+    """Per-element float64 acceptance bound for a sum evaluated by a tree of
+    additions at most `depth` deep: depth * 2^-53 * (running sum of |a|), plus
+    one rounding of the result (the standard bound for recursive summation)."""
+    return np.ldexp(abs_sums, -53) * (depth + 1) * (1 + 1e-6)
 
 
 def scan_f32(a: np.ndarray, exclusive: bool = False, reverse: bool = False,

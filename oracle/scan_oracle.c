@@ -17,7 +17,10 @@
  *
  * Integer element types add in uint32_t, i.e. modulo 2^32 (the paper is silent
  * on overflow; wrap-around is the reading taken).  32-bit signed data is the
- * same bit pattern.  64-bit integers likewise add in uint64_t, modulo 2^64.  Float32 inputs are accumulated in float64 (the paper
+ * same bit pattern.  64-bit integers likewise add in uint64_t, modulo 2^64.
+ * Float64 inputs are summed in double-double and rounded once (see
+ * oracle_scan_f64): the reference is the definition's exact prefix sum to
+ * within far less than one float64 rounding.  Float32 inputs are accumulated in float64 (the paper
  * notes that parallel float results may differ from the sequential ones; the
  * oracle therefore computes the sequential sum in a wider type and also
  * returns the running sum of absolute values, which sets the tolerance).
@@ -123,6 +126,46 @@ void oracle_scan_u64(const uint64_t *a, uint64_t *out, int64_t n, int exclusive)
         uint64_t x = a[i];
         if (exclusive) { out[i] = acc; acc += x; }
         else           { acc += x; out[i] = acc; }
+    }
+}
+
+/* Float64 inputs: the prefix sums of the definition, rounded once to float64.
+ * The running total is kept unevaluated as hi + lo (a double-double, about
+ * 106 significant bits): each input is added to hi with Knuth's TwoSum, which
+ * returns the rounded sum and its exact rounding error; the error joins lo
+ * and the pair is renormalised (Dekker's Fast2Sum), so hi is the total
+ * rounded to float64 and the accumulated error stays near n * 2^-106 *
+ * sum|a|, far below one float64 rounding.  abs_out[i] (may be NULL): the
+ * plain float64 running sum of |a|, the scale of the tolerance.  Forward
+ * only. */
+static void two_sum(double a, double b, double *s, double *e)
+{
+    double x = a + b;
+    double bv = x - a;
+    double av = x - bv;
+    *s = x;
+    *e = (a - av) + (b - bv);
+}
+
+void oracle_scan_f64(const double *a, double *out, double *abs_out, int64_t n, int exclusive)
+{
+    double hi = 0.0, lo = 0.0, aacc = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double x = a[i];
+        if (exclusive) {
+            out[i] = hi;
+            if (abs_out) abs_out[i] = aacc;
+        }
+        double s, e;
+        two_sum(hi, x, &s, &e);
+        e += lo;
+        hi = s + e;               /* Fast2Sum: |s| >= |e| after TwoSum */
+        lo = e - (hi - s);
+        aacc += fabs(x);
+        if (!exclusive) {
+            out[i] = hi;
+            if (abs_out) abs_out[i] = aacc;
+        }
     }
 }
 

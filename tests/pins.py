@@ -175,6 +175,56 @@ def pin_int64(scan64) -> list:
     return fails
 
 
+def pin_f64(scan_f64) -> list:
+    """scan_f64(a, exclusive) -> (sums float64, abs_sums float64): the exact
+    prefix sums rounded to float64."""
+    fails = []
+    g = golden_io.load("cancel_f64.txt", conv=float)
+    a = np.array(g["input"], dtype=np.float64)
+    s, _ = scan_f64(a, False)
+    _fcmp("golden cancel inclusive", s, g["inclusive"], fails)
+    s, _ = scan_f64(a, True)
+    _fcmp("golden cancel exclusive", s, g["exclusive"], fails)
+
+    # closed form: a_i = i (integers below 2^26: every partial sum exact)
+    n = 60_000
+    a = np.arange(n, dtype=np.float64)
+    k = np.arange(n, dtype=np.int64)
+    s, ab = scan_f64(a, False)
+    _fcmp("arithmetic progression inclusive", s, k * (k + 1) // 2, fails)
+    _fcmp("abs of a nonnegative input", ab, k * (k + 1) // 2, fails)
+    s, _ = scan_f64(a, True)
+    _fcmp("arithmetic progression exclusive", s, (k - 1) * k // 2, fails)
+
+    # exact rational prefix sums, rounded once, over a wide exponent range
+    rng = np.random.default_rng(19)
+    a = rng.standard_normal(400) * np.ldexp(1.0, rng.integers(-30, 30, size=400))
+    s, ab = scan_f64(a, False)
+    acc = Fraction(0)
+    for i, x in enumerate(a):
+        acc += Fraction(float(x))
+        ulp = Fraction(math.ulp(float(acc))) if acc != 0 else Fraction(0)
+        # correctly rounded up to the tiny double-double error
+        if abs(Fraction(float(s[i])) - acc) > ulp / 2 + Fraction(2.0**-100) * Fraction(float(ab[i])):
+            fails.append("rational exact sum at %d" % i)
+            break
+    # math.fsum (correctly rounded sum of floats) at sampled prefixes
+    a = rng.standard_normal(200_001) * 1e3
+    s, ab = scan_f64(a, False)
+    for i in list(range(0, a.size, 9_973)) + [a.size - 1]:
+        want = math.fsum(a[:i + 1].tolist())
+        if abs(float(s[i]) - want) > math.ulp(want) / 2 + 2.0**-95 * float(ab[i]):
+            fails.append("fsum prefix at %d" % i)
+            break
+    # exclusive is the inclusive result shifted by one, identity first
+    e, eab = scan_f64(a, True)
+    if e[0] != 0.0 or not np.array_equal(e[1:], s[:-1]):
+        fails.append("exclusive != shifted inclusive")
+    if abs(float(ab[-1]) - math.fsum(np.abs(a).tolist())) > a.size * 2.0**-53 * float(ab[-1]):
+        fails.append("abs sum total")
+    return fails
+
+
 def pin_int_inplace(scan_int_out) -> list:
     """scan_int_out(a, exclusive, reverse, out) with out == a."""
     fails = []

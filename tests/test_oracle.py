@@ -262,3 +262,52 @@ def _m64_no_wrap_signed(a, ex):
                                     _m64_no_wrap_signed])
 def test_pins_catch_int64_mutant(mutant):
     assert pins.pin_int64(mutant) != []
+
+
+# ---------------------------------------------------------------- float64
+
+def test_oracle_f64_pinned():
+    assert pins.pin_f64(lambda a, ex: oracle.scan_f64(a, exclusive=ex)) == []
+
+
+def _mf64_naive(a, ex):
+    # plain left-to-right float64 accumulation: loses the cancellation
+    v = np.asarray(a, dtype=np.float64)
+    c = np.add.accumulate(v)
+    ab = np.add.accumulate(np.abs(v))
+    if ex:
+        c = np.concatenate([[0.0], c[:-1]])
+        ab = np.concatenate([[0.0], ab[:-1]])
+    return c, ab
+
+
+def _mf64_f32_accumulator(a, ex):
+    v = np.asarray(a, dtype=np.float64)
+    c = np.cumsum(v.astype(np.float32), dtype=np.float32).astype(np.float64)
+    _, ab = oracle.scan_f64(a, exclusive=ex)
+    if ex:
+        c = np.concatenate([[0.0], c[:-1]])
+    return c, ab
+
+
+def _mf64_exclusive_is_inclusive(a, ex):
+    return oracle.scan_f64(a, exclusive=False)
+
+
+def _mf64_dropped_first(a, ex):
+    v = np.asarray(a, dtype=np.float64).copy()
+    if v.size:
+        v[0] = 0.0
+    return oracle.scan_f64(v, exclusive=ex)
+
+
+@pytest.mark.parametrize("mutant", [_mf64_naive, _mf64_f32_accumulator, _mf64_exclusive_is_inclusive,
+                                    _mf64_dropped_first])
+def test_pins_catch_f64_mutant(mutant):
+    assert pins.pin_f64(mutant) != []
+
+
+def test_f64_tolerance_scale():
+    ab = np.array([0.0, 1.0, 2.0**40])
+    t = oracle.f64_tolerance(ab, 127)
+    assert t[0] == 0.0 and np.allclose(t[1:], ab[1:] * 128 * 2.0**-53, rtol=1e-5)
