@@ -32,6 +32,10 @@ resident in HBM.  Prints ONE JSON line on stdout; progress goes to stderr.
   compaction the same input read as int32, elements > 0 kept (about half)
              by the fused one-pass compaction, against torch's masked select
              for context; results checked against the oracle
+  wide       64-bit elements, n = 2^28: uint64 full-range values (the bench
+             input as high halves, reversed as low halves) and float64
+             normal(0,1), inclusive, kernel time from HIP events at 16 bytes
+             per element; uint64 checked bit-exact, float64 within its bound
 Extra modes (not the headline line): --n, --dtype f32, --copy-calibration.
 """
 from __future__ import annotations
@@ -93,6 +97,7 @@ def parse():
     p.add_argument("--no-two-pass", action="store_true", help="skip the two-pass comparison")
     p.add_argument("--no-operators", action="store_true", help="skip the max / min / xor scans")
     p.add_argument("--no-compaction", action="store_true", help="skip the stream compaction")
+    p.add_argument("--no-wide", action="store_true", help="skip the 64-bit scans")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run only plain device copies of the scan's bytes (counter calibration)")
     return p.parse_args()
@@ -254,6 +259,11 @@ def main():
         comp = compaction_run(scan, torch, np, oracle, a, x, y, stream)
 
     del x, y
+    # ---------------------------------------------------------- 64-bit elements
+    wide = None
+    if not args.no_wide and args.dtype == "u32":
+        wide = wide_runs(scan, torch, np, oracle, a, stream)
+
     traffic = measured_traffic(n) if args.dtype == "u32" else None
     out = {
         "metric": "int32 scan GB/s at n=2^28 vs HBM peak; batched-segmented vs per-launch",
@@ -282,6 +292,7 @@ def main():
         "two_pass": two,
         "operators": ops,
         "compaction": comp,
+        "wide": wide,
     }
     print(json.dumps(out), flush=True)
 
@@ -319,6 +330,51 @@ def compaction_run(scan, torch, np, oracle, a, x, y, stream):
            "bytes_moved": int(moved), "torch_masked_select_us": round(ms_torch * 1e3, 1),
            "speedup_vs_torch": round(ms_torch / ms, 2), "results_equal_oracle": bool(ok)}
     log("compaction:", res)
+    return res
+
+
+def _median_ms(torch, fn, stream, reps):
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def wide_runs(scan, torch, np, oracle, a, stream):
+    """Inclusive scans of 2^28 uint64 and float64 elements (16 bytes moved per element)."""
+    n = a.size
+    res = {"workload": "inclusive scan, n=2^%d, uint64 full-range (wrapping) and float64 normal(0,1) seed 1004"
+                       % (n.bit_length() - 1)}
+    a64 = (a.astype(np.uint64) << np.uint64(32)) | a[::-1].astype(np.uint64)
+    x = torch.from_numpy(a64.view(np.int64)).to("cuda")
+    y = torch.empty_like(x)
+    ms = _median_ms(torch, lambda: scan.cumsum(x, out=y), stream, 20)
+    res["u64_us"] = round(ms * 1e3, 1)
+    res["u64_GBps"] = round(16.0 * n / (ms * 1e-3) / 1e9, 1)
+    res["u64_equal_oracle"] = bool(np.array_equal(y.cpu().numpy().view(np.uint64), oracle.scan_int64(a64)))
+    log("wide u64: %.1f us" % (ms * 1e3))
+    del a64
+    f = np.random.default_rng(1004).standard_normal(n)
+    x = torch.from_numpy(f).to("cuda")
+    y = torch.empty_like(x)
+    ms = _median_ms(torch, lambda: scan.cumsum(x, out=y), stream, 20)
+    res["f64_us"] = round(ms * 1e3, 1)
+    res["f64_GBps"] = round(16.0 * n / (ms * 1e-3) / 1e9, 1)
+    ref, ab = oracle.scan_f64(f)
+    depth = 8 * (-(-n // 32768)) + 128
+    err = np.abs(y.cpu().numpy() - ref)
+    res["f64_within_bound"] = bool(np.all(err <= oracle.f64_tolerance(ab, depth)))
+    res["f64_max_err_over_sum_abs"] = float(np.max(err / np.maximum(ab, 1e-300)))
+    log("wide f64: %.1f us" % (ms * 1e3))
+    del x, y
     return res
 
 

@@ -66,8 +66,10 @@ typedef enum {
 } scan_status_t;
 
 /* SCAN_I64 / SCAN_U64: 64-bit integer sums (wrapping modulo 2^64, the same
- * bits for both), scan_flat only: see scan_flat. */
-typedef enum { SCAN_I32 = 0, SCAN_U32 = 1, SCAN_F32 = 2, SCAN_I64 = 3, SCAN_U64 = 4 } scan_dtype_t;
+ * bits for both); SCAN_F64: float64 sums.  scan_flat only: see scan_flat. */
+typedef enum {
+    SCAN_I32 = 0, SCAN_U32 = 1, SCAN_F32 = 2, SCAN_I64 = 3, SCAN_U64 = 4, SCAN_F64 = 5
+} scan_dtype_t;
 
 /* Flag bits. */
 #define SCAN_EXCLUSIVE 0x1u  /* exclusive scan (identity first)              */
@@ -98,12 +100,16 @@ scan_status_t scan_exclusive_f32(const float *in, float *out, int64_t n, hipStre
 
 /* General flat scan: any dtype, flags = SCAN_EXCLUSIVE | SCAN_REVERSE, plus
  * an operator (SCAN_OP_*) for i32 / u32.
- * SCAN_I64 / SCAN_U64 (the Introduction's scan with + on 64-bit integers,
- * e.g. offsets past 2^32): in and out must be 16-byte aligned
- * (SCAN_ERROR_INVALID_VALUE otherwise), flags SCAN_EXCLUSIVE only (SCAN_REVERSE
- * or an operator: SCAN_ERROR_NOT_SUPPORTED); bit-exact, wrapping modulo 2^64.
- * The other entry points return SCAN_ERROR_NOT_SUPPORTED for these dtypes.
- * Uses the stream's workspace (two status words per 32768-element tile). */
+ * SCAN_I64 / SCAN_U64 / SCAN_F64 (the Introduction's scan with + on 64-bit
+ * elements, e.g. offsets past 2^32 or float64 data): in and out must be
+ * 16-byte aligned (SCAN_ERROR_INVALID_VALUE otherwise), flags SCAN_EXCLUSIVE
+ * only (SCAN_REVERSE or an operator: SCAN_ERROR_NOT_SUPPORTED).  Integers are
+ * bit-exact, wrapping modulo 2^64; a float64 result is a sum of the same
+ * inputs in another association, within (8 * tiles + 128) * 2^-53 times the
+ * running sum of |a| of the exact prefix sum (tiles = ceil(n / 32768); the
+ * depth of the addition tree, see the 64-bit kernel).  The other entry points
+ * return SCAN_ERROR_NOT_SUPPORTED for these dtypes.  Uses the stream's
+ * workspace (two status words per 32768-element tile). */
 scan_status_t scan_flat(const void *in, void *out, int64_t n, scan_dtype_t dtype,
                         uint32_t flags, hipStream_t stream);
 

@@ -16,7 +16,7 @@ import torch  # noqa: F401
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmi355scan.so")
 
-SCAN_I32, SCAN_U32, SCAN_F32, SCAN_I64, SCAN_U64 = 0, 1, 2, 3, 4
+SCAN_I32, SCAN_U32, SCAN_F32, SCAN_I64, SCAN_U64, SCAN_F64 = 0, 1, 2, 3, 4, 5
 SCAN_EXCLUSIVE, SCAN_REVERSE = 0x1, 0x2
 SCAN_TWO_PASS_PREFIX_INCREMENT, SCAN_TWO_PASS_ACCUMULATE_PREFIX = 0, 1
 SCAN_PRED_NONZERO, SCAN_PRED_GREATER = 0, 1

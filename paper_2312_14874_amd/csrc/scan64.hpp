@@ -1,12 +1,13 @@
-// Single-pass scans of 64-bit integers (wrapping modulo 2^64; int64 and
-// uint64 are the same bits): the same decoupled look-back as the 32-bit
-// kernel, with a tile's status held in two 64-bit words.  Each word carries
-// the 2-bit flag and one 32-bit half of the value and is moved by a single
-// relaxed atomic access; a reader takes the pair only when both halves carry
-// the same flag (flags only move forward, EMPTY -> AGG -> PREFIX, so a pair
-// with different flags is a publication in progress and reads as EMPTY), so
-// no fences are needed.  A lane holds two elements per 16-byte load; a
-// chunk is 128 elements.  Flat forward scans, inclusive or exclusive.
+// Single-pass scans of 64-bit elements: integers (wrapping modulo 2^64;
+// int64 and uint64 are the same bits) and float64 sums.  The same decoupled
+// look-back as the 32-bit kernel, with a tile's status held in two 64-bit
+// words.  Each word carries the 2-bit flag and one 32-bit half of the value
+// and is moved by a single relaxed atomic access; a reader takes the pair
+// only when both halves carry the same flag (flags only move forward, EMPTY
+// -> AGG -> PREFIX, so a pair with different flags is a publication in
+// progress and reads as EMPTY), so no fences are needed.  A lane holds two
+// elements per 16-byte load; a chunk is 128 elements.  Flat forward scans,
+// inclusive or exclusive.
 #pragma once
 #include "scan_device.hpp"
 
@@ -19,17 +20,58 @@ __device__ __forceinline__ uint64_t dpp64(uint64_t x) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Inclusive wave scan of 64-bit integers (the 32-bit wave_scan's steps on
-// both halves, then a 64-bit add).
-__device__ __forceinline__ uint64_t wave_scan64(uint64_t x) {
-  x += dpp64<0x111, 0xf>(x);
-  x += dpp64<0x112, 0xf>(x);
-  x += dpp64<0x114, 0xf>(x);
-  x += dpp64<0x118, 0xf>(x);
-  x += dpp64<0x142, 0xa>(x);
-  x += dpp64<0x143, 0xc>(x);
-  return x;
+// Inclusive wave scan of 64-bit integers: the 32-bit wave_scan's six steps
+// (row_shr 1, 2, 4, 8, row_bcast 15, 31), each x += (x of the lane the DPP
+// control names) done as a low-half add with carry out and a high-half add
+// with carry in that take their DPP operand directly.  Lanes without a source
+// lane, or in rows the row mask leaves out, are not written and keep x
+// (= x + 0); both adds of a step use the same control, so the carry is only
+// read in lanes that wrote it.  A DPP read needs two wait states after a VALU
+// write of its source register: the s_nops supply them inside the block and
+// on both sides of it (the compiler does not see the DPP reads here).
+#define MI355SCAN_DPP_ADD64(CTRL, TAIL)                        \
+  "v_add_co_u32_dpp %0, vcc, %0, %0 " CTRL "\n\t"             \
+  "v_addc_co_u32_dpp %1, vcc, %1, %1, vcc " CTRL "\n\t" TAIL
+__device__ __forceinline__ uint64_t wave_scan_u64(uint64_t x) {
+  uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+  asm("s_nop 1\n\t"
+      MI355SCAN_DPP_ADD64("row_shr:1 row_mask:0xf bank_mask:0xf", "s_nop 0\n\t")
+      MI355SCAN_DPP_ADD64("row_shr:2 row_mask:0xf bank_mask:0xf", "s_nop 0\n\t")
+      MI355SCAN_DPP_ADD64("row_shr:4 row_mask:0xf bank_mask:0xf", "s_nop 0\n\t")
+      MI355SCAN_DPP_ADD64("row_shr:8 row_mask:0xf bank_mask:0xf", "s_nop 0\n\t")
+      MI355SCAN_DPP_ADD64("row_bcast:15 row_mask:0xa bank_mask:0xf", "s_nop 0\n\t")
+      MI355SCAN_DPP_ADD64("row_bcast:31 row_mask:0xc bank_mask:0xf", "s_nop 1")
+      : "+v"(lo), "+v"(hi)
+      :
+      : "vcc");
+  return ((uint64_t)hi << 32) | lo;
 }
+#undef MI355SCAN_DPP_ADD64
+
+__device__ __forceinline__ double f64_of(uint64_t b) { return __builtin_bit_cast(double, b); }
+__device__ __forceinline__ uint64_t bits_of(double x) { return __builtin_bit_cast(uint64_t, x); }
+
+// The two element operations, on the 64-bit patterns: add and the inclusive
+// scan over the 64 lanes (identity: the all-zero pattern, 0 and +0.0).
+struct OpsAddU64 {
+  static __device__ __forceinline__ uint64_t add(uint64_t a, uint64_t b) { return a + b; }
+  static __device__ __forceinline__ uint64_t wave_scan(uint64_t x) { return wave_scan_u64(x); }
+};
+struct OpsAddF64 {
+  static __device__ __forceinline__ uint64_t add(uint64_t a, uint64_t b) { return bits_of(f64_of(a) + f64_of(b)); }
+  template <int CTRL, int ROW_MASK>
+  static __device__ __forceinline__ uint64_t step(uint64_t x) { return add(dpp64<CTRL, ROW_MASK>(x), x); }
+  // the 32-bit wave_scan's steps; lanes without a source add +0.0
+  static __device__ __forceinline__ uint64_t wave_scan(uint64_t x) {
+    x = step<0x111, 0xf>(x);
+    x = step<0x112, 0xf>(x);
+    x = step<0x114, 0xf>(x);
+    x = step<0x118, 0xf>(x);
+    x = step<0x142, 0xa>(x);
+    x = step<0x143, 0xc>(x);
+    return x;
+  }
+};
 
 __device__ __forceinline__ uint64_t lane_up1_64(uint64_t x) { return dpp64<0x138, 0xf>(x); }
 
@@ -72,6 +114,7 @@ __device__ __forceinline__ int64_t acquire_tile64(const KernelArgs &a, uint32_t 
 
 // Carry into tile t (one wave): sum of the aggregates back to the nearest
 // PREFIX, read 64 tiles per poll (lane l: tile t-1-l of the window).
+template <class Op>
 __device__ uint64_t look_back64(const uint64_t *st, int64_t t, uint32_t spin_limit, WsHeader *hdr) {
   const int lane = (int)(opaque_tid() & 63u);
   uint64_t acc = 0;
@@ -97,8 +140,8 @@ __device__ uint64_t look_back64(const uint64_t *st, int64_t t, uint32_t spin_lim
       continue;
     }
     // lanes 0..min(dP, 63) hold aggregates (and the PREFIX at dP)
-    const uint64_t part = readlane64(wave_scan64(lane <= dP ? v : 0ull), 63);
-    acc += part;
+    const uint64_t part = readlane64(Op::wave_scan(lane <= dP ? v : 0ull), 63);
+    acc = Op::add(acc, part);
     if (dP < 64) return acc;
     base -= 64;
   }
@@ -130,7 +173,7 @@ __device__ __forceinline__ uint64_t u64_of(uint32_t lo, uint32_t hi) { return ((
 
 // Resident grid, tiles from the device counter; ITEMS elements per thread
 // (2 per chunk and lane), the wave's span WSPAN = 64 * ITEMS elements.
-template <int BLOCK, int ITEMS, int MINW>
+template <class Op, int BLOCK, int ITEMS, int MINW>
 __global__ void __launch_bounds__(BLOCK, MINW) scan64_tiles(KernelArgs a) {
   static_assert(ITEMS % 2 == 0, "two elements per 16-byte group");
   constexpr int WAVES = BLOCK / 64;
@@ -173,16 +216,17 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan64_tiles(KernelArgs a) {
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       const uint64_t x0 = u64_of(R[c][0], R[c][1]);
-      const uint64_t x1 = u64_of(R[c][2], R[c][3]) + x0;
-      const uint64_t x = wave_scan64(x1);
-      const uint64_t off = lane_up1_64(x) + (c > 0 ? wsum : 0ull);
-      const uint64_t o0 = ex ? off : off + x0;
-      const uint64_t o1 = ex ? off + x0 : off + x1;
+      const uint64_t x1 = Op::add(u64_of(R[c][2], R[c][3]), x0);
+      const uint64_t x = Op::wave_scan(x1);
+      const uint64_t up = lane_up1_64(x);
+      const uint64_t off = c > 0 ? Op::add(up, wsum) : up;
+      const uint64_t o0 = ex ? off : Op::add(off, x0);
+      const uint64_t o1 = ex ? Op::add(off, x0) : Op::add(off, x1);
       R[c][0] = (uint32_t)o0;
       R[c][1] = (uint32_t)(o0 >> 32);
       R[c][2] = (uint32_t)o1;
       R[c][3] = (uint32_t)(o1 >> 32);
-      wsum += readlane64(x, 63);
+      wsum = c > 0 ? Op::add(wsum, readlane64(x, 63)) : readlane64(x, 63);
       asm volatile("" : "+v"(R[c]));
     }
     // wave totals: this wave's prefix and the tile's aggregate, left to right
@@ -192,7 +236,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan64_tiles(KernelArgs a) {
 #pragma unroll
     for (int w = 0; w < WAVES; ++w) {
       if (w == wave) wpre = agg;
-      agg += s_wtot[w];
+      agg = w > 0 ? Op::add(agg, s_wtot[w]) : s_wtot[w];
     }
     if (multi && wave == 0) {
       uint64_t *st = a.status + parity * a.capacity;
@@ -201,17 +245,17 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan64_tiles(KernelArgs a) {
         if (lane == 0) publish64(st, t, agg, kPrefix);
       } else {
         if (lane == 0) publish64(st, t, agg, kAgg);
-        carry = look_back64(st, t, a.spin_limit, a.hdr);
-        if (lane == 0) publish64(st, t, carry + agg, kPrefix);
+        carry = look_back64<Op>(st, t, a.spin_limit, a.hdr);
+        if (lane == 0) publish64(st, t, Op::add(carry, agg), kPrefix);
       }
       if (lane == 0) s_carry = carry;
     }
     __syncthreads();
-    const uint64_t win = (t > 0 ? s_carry : 0ull) + wpre;
+    const uint64_t win = t > 0 ? Op::add(s_carry, wpre) : wpre;
     const WaveSpan64<WSPAN> out(a.out, a.n, t * TILE + (int64_t)wave * WSPAN);
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      const uint64_t o0 = u64_of(R[c][0], R[c][1]) + win, o1 = u64_of(R[c][2], R[c][3]) + win;
+      const uint64_t o0 = Op::add(u64_of(R[c][0], R[c][1]), win), o1 = Op::add(u64_of(R[c][2], R[c][3]), win);
       R[c][0] = (uint32_t)o0;
       R[c][1] = (uint32_t)(o0 >> 32);
       R[c][2] = (uint32_t)o1;

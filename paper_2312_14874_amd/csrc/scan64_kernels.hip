@@ -5,8 +5,9 @@
 namespace mi355scan {
 
 // 512 threads x 64 elements per tile (two per 16-byte group), one resident
-// workgroup per CU
-const void *kScan64 = (const void *)&scan64_tiles<512, 64, 2>;
+// workgroup per CU; [0 = integer, 1 = float64]
+const void *kScan64[2] = {(const void *)&scan64_tiles<OpsAddU64, 512, 64, 2>,
+                          (const void *)&scan64_tiles<OpsAddF64, 512, 64, 2>};
 const int kScan64Block = 512, kScan64Items = 64;
 
 }  // namespace mi355scan

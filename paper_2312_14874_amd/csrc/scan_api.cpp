@@ -348,9 +348,10 @@ scan_status_t launch(const Call &c, hipStream_t stream, Workspace *ws_override, 
   return SCAN_SUCCESS;
 }
 
-// 64-bit integer scans: one resident launch of the 64-bit kernel over
-// 32768-element tiles (tiles from the counter), two status words per tile.
-scan_status_t flat64(const void *in, void *out, int64_t n, uint32_t flags, hipStream_t stream) {
+// 64-bit scans: one resident launch of the 64-bit kernel over 32768-element
+// tiles (tiles from the counter), two status words per tile.
+scan_status_t flat64(const void *in, void *out, int64_t n, scan_dtype_t dt, uint32_t flags,
+                     hipStream_t stream) {
   int r = check_flags(flags);
   if (r == kOk) r = check_flat_sz(in, out, n, 8);
   if (r != kOk) return st(r);
@@ -370,7 +371,8 @@ scan_status_t flat64(const void *in, void *out, int64_t n, uint32_t flags, hipSt
     s = stream_ws(dev, stream, 2 * T, &ws);
     if (s != SCAN_SUCCESS) return s;
   }
-  const int64_t grid = std::min<int64_t>(T, resident_grid(kScan64, kScan64Block, di.cus, 0, 100));
+  const void *fn = kScan64[dt == SCAN_F64 ? 1 : 0];
+  const int64_t grid = std::min<int64_t>(T, resident_grid(fn, kScan64Block, di.cus, 0, 100));
   KernelArgs a;
   std::memset(&a, 0, sizeof(a));
   a.in = in;
@@ -387,13 +389,13 @@ scan_status_t flat64(const void *in, void *out, int64_t n, uint32_t flags, hipSt
   }
   a.exclusive = (flags & SCAN_EXCLUSIVE) ? 1u : 0u;
   void *args[] = {&a};
-  hipError_t e = hipLaunchKernel(kScan64, dim3((unsigned)grid), dim3(kScan64Block), args, 0, stream);
+  hipError_t e = hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kScan64Block), args, 0, stream);
   return e == hipSuccess ? SCAN_SUCCESS : hip_fail(e);
 }
 
 scan_status_t flat(const void *in, void *out, int64_t n, scan_dtype_t dt, uint32_t flags,
                    hipStream_t stream) {
-  if (is_dtype64((int)dt)) return flat64(in, out, n, flags, stream);
+  if (is_dtype64((int)dt)) return flat64(in, out, n, dt, flags, stream);
   int r = check_dtype((int)dt);
   if (r == kOk) r = check_flags(flags);
   if (r == kOk) r = check_flat(in, out, n);

@@ -55,8 +55,9 @@ struct CompactKernels {
 };
 extern const CompactKernels kCompact;
 
-// 64-bit integer scans (flat, forward, 16-byte aligned buffers).
-extern const void *kScan64;
+// 64-bit scans (flat, forward, 16-byte aligned buffers): [0 = integer sum,
+// 1 = float64 sum].
+extern const void *kScan64[2];
 extern const int kScan64Block, kScan64Items;
 
 }  // namespace mi355scan

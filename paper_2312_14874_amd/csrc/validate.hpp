@@ -37,8 +37,8 @@ int check_flags(uint32_t flags);
 int check_flat(const void *in, const void *out, int64_t n);
 // the same for elements of esize bytes (aligned to esize)
 int check_flat_sz(const void *in, const void *out, int64_t n, int esize);
-// 64-bit integer dtypes (3 = int64, 4 = uint64): scan_flat only
-inline bool is_dtype64(int dtype) { return dtype == 3 || dtype == 4; }
+// 64-bit dtypes (3 = int64, 4 = uint64, 5 = float64): scan_flat only
+inline bool is_dtype64(int dtype) { return dtype >= 3 && dtype <= 5; }
 // segmented batch: offsets (S+1 int64, 8-byte aligned) required when n > 0
 int check_segmented(const void *in, const void *out, const void *offsets,
                     int64_t num_segments, int64_t n);

@@ -10,14 +10,15 @@ import ctypes
 import torch
 
 from ._lib import (SCAN_EXCLUSIVE, SCAN_F32, SCAN_I32, SCAN_I64, SCAN_PRED_GREATER, SCAN_PRED_NONZERO,
-                   SCAN_REVERSE, SCAN_TWO_PASS_ACCUMULATE_PREFIX, SCAN_TWO_PASS_PREFIX_INCREMENT, SCAN_U32,
-                   SCAN_U64, check, lib)
+                   SCAN_F64, SCAN_REVERSE, SCAN_TWO_PASS_ACCUMULATE_PREFIX, SCAN_TWO_PASS_PREFIX_INCREMENT,
+                   SCAN_U32, SCAN_U64, check, lib)
 
 _DTYPES = {torch.int32: SCAN_I32, torch.float32: SCAN_F32}
 if hasattr(torch, "uint32"):
     _DTYPES[torch.uint32] = SCAN_U32
-# 64-bit integers: forward +-scans of cumsum only (the library refuses the rest)
+# 64-bit elements: forward +-scans of cumsum only (the library refuses the rest)
 _DTYPES[torch.int64] = SCAN_I64
+_DTYPES[torch.float64] = SCAN_F64
 if hasattr(torch, "uint64"):
     _DTYPES[torch.uint64] = SCAN_U64
 
@@ -42,7 +43,7 @@ def _check_tensor(x: torch.Tensor, name: str) -> int:
     if not x.is_cuda:
         raise ValueError("%s must be a GPU tensor" % name)
     if x.dtype not in _DTYPES:
-        raise TypeError("%s: unsupported dtype %s (int32, uint32, float32, int64, uint64)" % (name, x.dtype))
+        raise TypeError("%s: unsupported dtype %s (int32, uint32, float32, int64, uint64, float64)" % (name, x.dtype))
     if not x.is_contiguous():
         raise ValueError("%s must be contiguous" % name)
     return _DTYPES[x.dtype]
@@ -71,9 +72,9 @@ def cumsum(x: torch.Tensor, exclusive: bool = False, reverse: bool = False, out=
     """Scan of a contiguous int32 / uint32 / float32 GPU tensor (flattened).
 
     op: "sum" (any dtype), or "max" / "min" / "xor" for int32 (signed) and
-    uint32.  out may be x itself (in place).  int64 / uint64 tensors take
-    forward +-scans (exclusive or not), wrapping modulo 2^64, and must start
-    on a 16-byte boundary."""
+    uint32.  out may be x itself (in place).  int64 / uint64 / float64
+    tensors take forward +-scans (exclusive or not; integers wrap modulo
+    2^64) and must start on a 16-byte boundary."""
     dt = _check_tensor(x, "x")
     out = _out_like(x, out)
     with torch.cuda.device(x.device):

@@ -119,7 +119,7 @@ def test_two_pass_argument_errors():
     assert f(4096, 8192, 10, 0, 2, 1, 0, None) == 5                 # reverse: not supported
 
 
-I64, U64 = 3, 4
+I64, U64, F64 = 3, 4, 5
 
 
 def test_int64_argument_errors():
@@ -133,10 +133,15 @@ def test_int64_argument_errors():
     assert f(4096, 8192, 10, I64, REV, None) == NOT_SUPPORTED       # forward only
     assert f(4096, 8192, 10, U64, OP_MAX, None) == NOT_SUPPORTED    # + only
     assert f(4096, 8192, 10, I64, 0x10, None) == INVALID            # unknown flag
+    assert f(4104, 8192, 10, F64, 0, None) == INVALID               # float64: 16-byte alignment too
+    assert f(4096, 8192, 10, F64, REV | EXC, None) == NOT_SUPPORTED
+    assert f(4096, 8192, 10, F64, OP_XOR, None) == NOT_SUPPORTED
     # the other entry points take 32-bit dtypes only
     assert L.lib.scan_segmented_batch(4096, 8192, 16, 1, 10, I64, 0, None) == NOT_SUPPORTED
     assert L.lib.scan_two_pass(4096, 8192, 10, U64, 0, 1, 0, None) == NOT_SUPPORTED
     assert L.lib.scan_compact(4096, 8192, 10, I64, 0, 0, 16, None) == NOT_SUPPORTED
+    assert L.lib.scan_segmented_batch(4096, 8192, 16, 1, 10, F64, 0, None) == NOT_SUPPORTED
+    assert L.lib.scan_selected_config(F64, 0, 0, 100) == -1
 
 
 def test_other_argument_errors():

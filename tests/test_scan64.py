@@ -99,3 +99,71 @@ def test_torch_binding():
 
 def test_full_size():
     check(data(1 << 28, 6600), exclusive=False)
+
+
+# ---------------------------------------------------------------- float64
+
+F64 = 5
+
+
+def run_f64(a: np.ndarray, exclusive=False, inplace=False) -> np.ndarray:
+    x = torch.empty(a.size + 2, dtype=torch.float64, device="cuda")[2:]
+    x.copy_(torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)))
+    out = x if inplace else torch.zeros(a.size + 2, dtype=torch.float64, device="cuda")[2:]
+    check_status(lib().scan_flat(x.data_ptr(), out.data_ptr(), a.size, F64, 1 if exclusive else 0, stream()),
+                 "scan_flat f64 n=%d" % a.size)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def check_f64(a, exclusive=False, **kw):
+    """Within the recursive-summation bound of the kernel's addition tree: at
+    most 8 levels per tile of the look-back chain plus 128 inside a tile."""
+    ref, ab = oracle.scan_f64(a, exclusive=exclusive)
+    got = run_f64(a, exclusive, **kw)
+    depth = 8 * (-(-a.size // TILE)) + 128
+    tol = oracle.f64_tolerance(ab, depth)
+    err = np.abs(got - ref)
+    bad = np.nonzero(~(err <= tol))[0]
+    assert bad.size == 0, "n=%d ex=%d: %d out of bound, first %d: got %r want %r tol %r" % (
+        a.size, exclusive, bad.size, bad[0], got[bad[0]], ref[bad[0]], tol[bad[0]])
+
+
+def normal_f64(n, seed):
+    return np.random.default_rng(seed).standard_normal(n)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 129, TILE - 1, TILE, TILE + 1, 5 * TILE + 777, (1 << 20) + 3])
+@pytest.mark.parametrize("exclusive", [False, True])
+def test_f64_ragged(n, exclusive):
+    check_f64(normal_f64(n, 6700 + n % 89), exclusive)
+
+
+def test_f64_values():
+    g = np.random.default_rng(6800)
+    n = 23 * TILE + 1001
+    # integer-valued (every partial sum exact in any order): equal to the oracle
+    a = g.integers(-1000, 1001, size=n).astype(np.float64)
+    assert not first_mismatch(run_f64(a), oracle.scan_f64(a)[0])
+    # wide exponent range, and cancelling pairs
+    check_f64(g.standard_normal(n) * np.ldexp(1.0, g.integers(-40, 40, size=n)))
+    b = g.standard_normal(n)
+    b[1::2] = -b[0::2][: b[1::2].size]
+    check_f64(b, exclusive=True)
+
+
+def test_f64_in_place():
+    check_f64(normal_f64(9 * TILE + 3, 6900), inplace=True)
+
+
+def test_f64_torch_binding():
+    import paper_2312_14874_amd as m
+    a = normal_f64(4 * TILE + 5, 7000)
+    x = torch.from_numpy(a).cuda()
+    got = m.cumsum(x).cpu().numpy()
+    ref, ab = oracle.scan_f64(a)
+    assert np.all(np.abs(got - ref) <= oracle.f64_tolerance(ab, 8 * 5 + 128))
+
+
+def test_f64_full_size():
+    check_f64(normal_f64(1 << 28, 7100))
