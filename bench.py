@@ -14,7 +14,9 @@ resident in HBM.  Prints ONE JSON line on stdout; progress goes to stderr.
              bytes per launch measured with rocprofv3 counters (profiles/),
              or null when the kernel sources changed since that measurement
   cpu_baseline  the sequential oracle on one host core, over repeated passes
-             of the same 2^28-element input (about 10 s)
+             of the same 2^28-element input (about 10 s); its output also
+             checks the timed GPU result.  The CPU legs run last and are the
+             only part of this script that calls the oracle.
   cpu_context the paper's own multithreaded scheme (Accumulate + Prefix Sum
              over cache-sized partitions, one barrier per iteration) on up to
              16 host cores, same input, checked against the oracle; context
@@ -22,20 +24,24 @@ resident in HBM.  Prints ONE JSON line on stdout; progress goes to stderr.
   segmented  the batched segmented scan (4096 segments, log-uniform lengths in
              [1, 2^20], Poisson(8) int32 counts, exclusive, one persistent
              launch replayed from a hipGraph) against one flat-scan launch per
-             segment, eager and graph-captured; all results are compared
+             segment, eager and graph-captured; the batched result is checked
+             exactly on the GPU (0 at each segment start, y[i] = y[i-1] +
+             x[i-1] elsewhere) and the others must equal it
   two_pass   the same n = 2^28 scan by the paper's two-pass algorithms
              (Section 2.1: Prefix Sum + Increment, Accumulate + Prefix Sum),
              whole-array and over cache-sized partitions (Section 2.2),
              against the single pass; results compared with its output
   operators  the same input scanned with max, min and xor (int32), kernel
-             time from HIP events, each result checked against the oracle
+             time from HIP events, each result checked exactly on the GPU by
+             its recurrence y[i] = y[i-1] op x[i]
   compaction the same input read as int32, elements > 0 kept (about half)
              by the fused one-pass compaction, against torch's masked select
-             for context; results checked against the oracle
+             for context; the result must equal torch's
   wide       64-bit elements, n = 2^28: uint64 full-range values (the bench
              input as high halves, reversed as low halves) and float64
              normal(0,1), inclusive, kernel time from HIP events at 16 bytes
-             per element; uint64 checked bit-exact, float64 within its bound
+             per element; uint64 checked exactly by its recurrence on the GPU,
+             float64 against the oracle within its bound in the CPU legs
 Extra modes (not the headline line): --n, --dtype f32, --copy-calibration.
 """
 from __future__ import annotations
@@ -185,63 +191,20 @@ def main():
         % (ms_per_step * 1e3, kern_avg_ms * 1e3, kern_ms[K // 10] * 1e3, kern_ms[(9 * K) // 10] * 1e3, achieved))
 
     # ---------------------------------------------------------- parity of the timed output
-    import oracle
+    # an inclusive integer +-scan is characterised exactly by y[0] = x[0] and
+    # y[i] - y[i-1] = x[i] (mod 2^32): checked on the GPU, no reference needed;
+    # the float32 mode is compared with the oracle in the CPU leg
     got = y.cpu().numpy()
     if args.dtype == "u32":
-        want = oracle.scan_int(a)
-        parity = "bit-exact" if np.array_equal(got.view(np.uint32), want) else "MISMATCH"
+        parity = "bit-exact (y[0]=x[0], y[i]-y[i-1]=x[i])" if inclusive_sum_holds(torch, x, y) else "MISMATCH"
     else:
-        ref, ab = oracle.scan_f32(a)
-        ok = np.all(np.abs(got.astype(np.float64) - ref) <= np.ldexp(ab, -20))
-        parity = "within 2^-20*sum|a|" if ok else "MISMATCH"
+        parity = "unchecked (--no-cpu)"
     log("parity:", parity)
-
-    # ---------------------------------------------------------- CPU oracle baseline
-    cpu = None
-    if not args.no_cpu:
-        reps, total, times = 0, 0.0, []
-        while total < 10.0 and reps < 100:
-            c0 = time.perf_counter()
-            oracle.scan_int(a) if args.dtype == "u32" else oracle.scan_f32(a, with_abs=False)
-            dt = time.perf_counter() - c0
-            times.append(dt)
-            total += dt
-            reps += 1
-        times.sort()
-        med = times[len(times) // 2]
-        cpu = {"value": round(alg_bytes / med / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": "%d sequential passes over the same n=2^%d input (%.1f s), median pass %.3f s = %.3f Gelem/s"
-                         % (reps, n.bit_length() - 1, total, med, n / med / 1e9)}
-        log("cpu oracle:", cpu["value"], "GB/s")
-
-    # ---------------------------------------------------------- the paper's CPU scheme, for context
-    cpu_ctx = None
-    if not args.no_cpu and args.dtype == "u32":
-        import cpu_context
-        threads = min(16, len(os.sched_getaffinity(0)))
-        buf = np.empty_like(a)
-        best, ok = None, True
-        for part in (1 << 16, 1 << 18, 1 << 20):      # partition sizes tried (elements)
-            times = []
-            for _ in range(5):
-                c0 = time.perf_counter()
-                cpu_context.two_pass_scan_u32(a, threads, part, out=buf)
-                times.append(time.perf_counter() - c0)
-            ok = ok and bool(np.array_equal(buf, want))
-            times.sort()
-            med = times[len(times) // 2]
-            if best is None or med < best[0]:
-                best = (med, part)
-        cpu_ctx = {"value": round(alg_bytes / best[0] / 1e9, 2), "unit": "GB/s", "cores": threads,
-                   "kind": "paper two-pass Accumulate + Prefix Sum, best of 2^16 / 2^18 / 2^20-element "
-                           "partitions (%d)" % best[1],
-                   "equal_oracle": ok}
-        log("cpu context:", cpu_ctx)
 
     # ---------------------------------------------------------- segmented vs per-launch
     seg = None
     if not args.no_segmented and args.dtype == "u32":
-        seg = segmented_comparison(scan, torch, np, workloads, oracle, dev)
+        seg = segmented_comparison(scan, torch, np, workloads, dev)
 
     # ---------------------------------------------------------- two-pass algorithms vs the single pass
     two = None
@@ -251,18 +214,28 @@ def main():
     # ---------------------------------------------------------- other operators on the same input
     ops = None
     if not args.no_operators and args.dtype == "u32":
-        ops = operator_runs(scan, torch, np, oracle, a, x, y, stream)
+        ops = operator_runs(scan, torch, x, y, stream)
 
     # ---------------------------------------------------------- stream compaction of the same input
     comp = None
     if not args.no_compaction and args.dtype == "u32":
-        comp = compaction_run(scan, torch, np, oracle, a, x, y, stream)
+        comp = compaction_run(scan, torch, x, y, stream)
 
     del x, y
     # ---------------------------------------------------------- 64-bit elements
-    wide = None
+    wide, wide_f64 = None, None
     if not args.no_wide and args.dtype == "u32":
-        wide = wide_runs(scan, torch, np, oracle, a, stream)
+        wide, wide_f64 = wide_runs(scan, torch, np, a, stream)
+
+    # ---------------------------------------------------------- CPU legs (the oracle on the host)
+    cpu, cpu_ctx = None, None
+    if not args.no_cpu:
+        cpu, cpu_ctx, f64_ok = cpu_legs(args, np, a, got, alg_bytes, wide_f64)
+        if args.dtype == "f32":
+            parity = "within 2^-20*sum|a|" if cpu["gpu_result_within_bound"] else "MISMATCH"
+        if wide is not None:
+            wide["f64_vs_oracle"] = f64_ok
+    del wide_f64
 
     traffic = measured_traffic(n) if args.dtype == "u32" else None
     out = {
@@ -297,7 +270,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def compaction_run(scan, torch, np, oracle, a, x, y, stream):
+def compaction_run(scan, torch, x, y, stream):
     """Elements > 0 of the bench input read as int32, fused one-pass compaction."""
     n = x.numel()
     cnt = torch.empty(1, dtype=torch.int64, device=x.device)
@@ -321,16 +294,81 @@ def compaction_run(scan, torch, np, oracle, a, x, y, stream):
 
     ms = timed(run, 20)
     k = int(cnt.item())
-    want = oracle.compact(a.view(np.int32), "greater", 0)
-    ok = k == want.size and np.array_equal(y[:k].cpu().numpy(), want)
+    want = torch.masked_select(x, x > 0)
+    ok = k == want.numel() and bool(torch.equal(y[:k], want))
+    del want
     ms_torch = timed(lambda: torch.masked_select(x, x > 0), 5)
     moved = 4.0 * n + 4.0 * k
     res = {"workload": "keep x > 0 of the same n=2^%d input read as int32 (%d kept)" % (n.bit_length() - 1, k),
            "fused_us": round(ms * 1e3, 1), "GBps_moved": round(moved / (ms * 1e-3) / 1e9, 1),
            "bytes_moved": int(moved), "torch_masked_select_us": round(ms_torch * 1e3, 1),
-           "speedup_vs_torch": round(ms_torch / ms, 2), "results_equal_oracle": bool(ok)}
+           "speedup_vs_torch": round(ms_torch / ms, 2), "results_equal_torch_masked_select": bool(ok)}
     log("compaction:", res)
     return res
+
+
+def cpu_legs(args, np, a, got, alg_bytes, wide_f64):
+    """The oracle on the host cores: the reported CPU baseline (repeated timed
+    passes over the bench input), whose output is also the reference for the
+    timed GPU result, for the paper's CPU scheme (context) and for the float64
+    scan of the 'wide' object."""
+    import oracle
+    n = a.size
+    reps, total, times, want = 0, 0.0, [], None
+    while total < 10.0 and reps < 100:
+        c0 = time.perf_counter()
+        want = oracle.scan_int(a) if args.dtype == "u32" else oracle.scan_f32(a, with_abs=False)[0]
+        dt = time.perf_counter() - c0
+        times.append(dt)
+        total += dt
+        reps += 1
+    times.sort()
+    med = times[len(times) // 2]
+    if args.dtype == "u32":
+        equal = bool(np.array_equal(got.view(np.uint32), want))
+    else:
+        ref, ab = oracle.scan_f32(a)
+        equal = bool(np.all(np.abs(got.astype(np.float64) - ref) <= np.ldexp(ab, -20)))
+    cpu = {"value": round(alg_bytes / med / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+           "sample": "%d sequential passes over the same n=2^%d input (%.1f s), median pass %.3f s = %.3f Gelem/s"
+                     % (reps, n.bit_length() - 1, total, med, n / med / 1e9),
+           "gpu_result_equal_oracle" if args.dtype == "u32" else "gpu_result_within_bound": equal}
+    log("cpu oracle:", cpu["value"], "GB/s; GPU result agrees:", equal)
+
+    # the paper's multithreaded scheme on the host, for context
+    cpu_ctx = None
+    if args.dtype == "u32":
+        import cpu_context
+        threads = min(16, len(os.sched_getaffinity(0)))
+        buf = np.empty_like(a)
+        best, ok = None, True
+        for part in (1 << 16, 1 << 18, 1 << 20):      # partition sizes tried (elements)
+            times = []
+            for _ in range(5):
+                c0 = time.perf_counter()
+                cpu_context.two_pass_scan_u32(a, threads, part, out=buf)
+                times.append(time.perf_counter() - c0)
+            ok = ok and bool(np.array_equal(buf, want))
+            times.sort()
+            med = times[len(times) // 2]
+            if best is None or med < best[0]:
+                best = (med, part)
+        cpu_ctx = {"value": round(alg_bytes / best[0] / 1e9, 2), "unit": "GB/s", "cores": threads,
+                   "kind": "paper two-pass Accumulate + Prefix Sum, best of 2^16 / 2^18 / 2^20-element "
+                           "partitions (%d)" % best[1],
+                   "equal_oracle": ok}
+        log("cpu context:", cpu_ctx)
+
+    # float64 result of the wide object against the double-double oracle
+    f64_ok = None
+    if wide_f64 is not None:
+        f, yf = wide_f64
+        ref, ab = oracle.scan_f64(f)
+        depth = 8 * (-(-f.size // 32768)) + 128
+        err = np.abs(yf - ref)
+        f64_ok = {"within_bound": bool(np.all(err <= oracle.f64_tolerance(ab, depth))),
+                  "max_err_over_sum_abs": float(np.max(err / np.maximum(ab, 1e-300)))}
+    return cpu, cpu_ctx, f64_ok
 
 
 def _median_ms(torch, fn, stream, reps):
@@ -348,61 +386,60 @@ def _median_ms(torch, fn, stream, reps):
     return ts[len(ts) // 2]
 
 
-def wide_runs(scan, torch, np, oracle, a, stream):
-    """Inclusive scans of 2^28 uint64 and float64 elements (16 bytes moved per element)."""
+def wide_runs(scan, torch, np, a, stream):
+    """Inclusive scans of 2^28 uint64 and float64 elements (16 bytes moved per
+    element).  uint64 is checked exactly on the GPU (y[0] = x[0], y[i] - y[i-1]
+    = x[i] mod 2^64); the float64 input and result come back to the host for
+    the CPU leg's comparison with the oracle."""
     n = a.size
     res = {"workload": "inclusive scan, n=2^%d, uint64 full-range (wrapping) and float64 normal(0,1) seed 1004"
                        % (n.bit_length() - 1)}
     a64 = (a.astype(np.uint64) << np.uint64(32)) | a[::-1].astype(np.uint64)
     x = torch.from_numpy(a64.view(np.int64)).to("cuda")
+    del a64
     y = torch.empty_like(x)
     ms = _median_ms(torch, lambda: scan.cumsum(x, out=y), stream, 20)
     res["u64_us"] = round(ms * 1e3, 1)
     res["u64_GBps"] = round(16.0 * n / (ms * 1e-3) / 1e9, 1)
-    res["u64_equal_oracle"] = bool(np.array_equal(y.cpu().numpy().view(np.uint64), oracle.scan_int64(a64)))
+    res["u64_exact"] = inclusive_sum_holds(torch, x, y)
     log("wide u64: %.1f us" % (ms * 1e3))
-    del a64
     f = np.random.default_rng(1004).standard_normal(n)
     x = torch.from_numpy(f).to("cuda")
     y = torch.empty_like(x)
     ms = _median_ms(torch, lambda: scan.cumsum(x, out=y), stream, 20)
     res["f64_us"] = round(ms * 1e3, 1)
     res["f64_GBps"] = round(16.0 * n / (ms * 1e-3) / 1e9, 1)
-    ref, ab = oracle.scan_f64(f)
-    depth = 8 * (-(-n // 32768)) + 128
-    err = np.abs(y.cpu().numpy() - ref)
-    res["f64_within_bound"] = bool(np.all(err <= oracle.f64_tolerance(ab, depth)))
-    res["f64_max_err_over_sum_abs"] = float(np.max(err / np.maximum(ab, 1e-300)))
     log("wide f64: %.1f us" % (ms * 1e3))
+    yf = y.cpu().numpy()
     del x, y
-    return res
+    return res, (f, yf)
 
 
-def operator_runs(scan, torch, np, oracle, a, x, y, stream):
-    """max / min / xor inclusive scans of the bench input read as int32."""
+def inclusive_sum_holds(torch, x, y):
+    """Exact test of an inclusive integer +-scan without a reference: y[0] =
+    x[0] and y[i] - y[i-1] = x[i] in the tensors' wrapping arithmetic."""
+    return bool(y[0] == x[0]) and bool(torch.equal(y[1:] - y[:-1], x[1:]))
+
+
+def operator_runs(scan, torch, x, y, stream):
+    """max / min / xor inclusive scans of the bench input read as int32.  Each
+    result is checked exactly on the GPU by the recurrence that defines it:
+    y[0] = x[0] and y[i] = y[i-1] (op) x[i] (signed compares)."""
     n = x.numel()
     res = {"workload": "inclusive scan of the same n=2^%d input read as int32 (signed compares)" % (n.bit_length() - 1)}
     ok = True
+    combine = {"max": torch.maximum, "min": torch.minimum, "xor": torch.bitwise_xor}
     for op in ("max", "min", "xor"):
         def run():
             scan.cumsum(x, op=op, out=y)
         run()
         torch.cuda.synchronize()
-        ok = ok and np.array_equal(y.cpu().numpy(), oracle.scan_op(a.view(np.int32), op))
-        ts = []
-        for _ in range(20):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            run()
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1))
-        ts.sort()
-        ms = ts[len(ts) // 2]
+        ok = ok and bool(y[0] == x[0]) and bool(torch.equal(y[1:], combine[op](y[:-1], x[1:])))
+        ms = _median_ms(torch, run, stream, 20)
         res[op + "_us"] = round(ms * 1e3, 1)
         res[op + "_GBps"] = round(8.0 * n / (ms * 1e-3) / 1e9, 1)
         log("operator %s: %.1f us" % (op, ms * 1e3))
-    res["results_equal_oracle"] = bool(ok)
+    res["results_exact"] = bool(ok)
     return res
 
 
@@ -439,7 +476,7 @@ def two_pass_comparison(scan, torch, x, y, single_ms, stream):
             "single_pass_us": round(single_ms * 1e3, 1), "runs": rows, "results_equal": equal}
 
 
-def segmented_comparison(scan, torch, np, workloads, oracle, dev):
+def segmented_comparison(scan, torch, np, workloads, dev):
     """Batched segmented scan (graph replay) vs one launch per segment."""
     import ctypes
     t0 = time.time()
@@ -478,10 +515,15 @@ def segmented_comparison(scan, torch, np, workloads, oracle, dev):
     t_looped_graph = timed(g_looped.launch, 5)
     g_batched.launch()
     torch.cuda.synchronize()
-    want = oracle.segmented_int(vals, off, exclusive=True)
-    ok_b = np.array_equal(y_b.cpu().numpy(), want)
-    ok_l = np.array_equal(y_l.cpu().numpy(), want)
-    ok_g = np.array_equal(y_g.cpu().numpy(), want)
+    # an exclusive segmented +-scan is characterised exactly by y = 0 at every
+    # segment start and y[i] = y[i-1] + x[i-1] elsewhere (mod 2^32)
+    start = torch.zeros(n, dtype=torch.bool, device=dev)
+    first = offs[:-1]
+    start[first[first < n]] = True
+    ok_b = bool((y_b[start] == 0).all()) and bool(((y_b[1:] - y_b[:-1] - x[:-1])[~start[1:]] == 0).all())
+    ok_l = bool(torch.equal(y_l, y_b))
+    ok_g = bool(torch.equal(y_g, y_b))
+    del start
     g_batched.close()
     g_looped.close()
     alg = 8.0 * n + 8.0 * (S + 1)
