@@ -58,6 +58,8 @@ def _load():
         lib.oracle_compact_u32.restype = I64
         lib.oracle_scan_u64.argtypes = [P, P, I64, I]
         lib.oracle_scan_u64.restype = None
+        lib.oracle_partition_u32.argtypes = [P, P, I64, I, I, ctypes.c_uint32]
+        lib.oracle_partition_u32.restype = I64
         lib.oracle_scan_f64.argtypes = [P, P, P, I64, I]
         lib.oracle_scan_f64.restype = None
         for f in (lib.oracle_scan_u32, lib.oracle_scan_f32_f64,
@@ -213,6 +215,19 @@ def compact(a: np.ndarray, predicate: str = "nonzero", threshold=0) -> np.ndarra
     dst = np.empty_like(src)
     k = _load().oracle_compact_u32(_ptr(src), _ptr(dst), src.size, PREDICATES[predicate], dt, int(thr))
     return dst[:k].view(a.dtype).copy()
+
+
+def partition(a: np.ndarray, predicate: str = "nonzero", threshold=0):
+    """Two-way partition of a (int32 / uint32 / float32) by the predicate of
+    compact: returns (out, k) with the kept elements in out[:k] in input order
+    and the others in out[k:] in reverse input order."""
+    a = np.ascontiguousarray(a)
+    dt = {np.dtype(np.int32): 0, np.dtype(np.uint32): 1, np.dtype(np.float32): 2}[a.dtype]
+    thr = np.array([threshold], dtype=a.dtype).view(np.uint32)[0]
+    src = a.view(np.uint32)
+    dst = np.empty_like(src)
+    k = _load().oracle_partition_u32(_ptr(src), _ptr(dst), src.size, PREDICATES[predicate], dt, int(thr))
+    return dst.view(a.dtype), int(k)
 
 
 def f32_tolerance(abs_sums: np.ndarray) -> np.ndarray:

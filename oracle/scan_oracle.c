@@ -249,3 +249,20 @@ int64_t oracle_compact_u32(const uint32_t *a, uint32_t *out, int64_t n, int pred
     }
     return k;
 }
+
+/* Two-way partition by the same predicate (the Introduction's partitioning
+ * step: new offsets from a bitmap): element i goes to out[k] if kept, k being
+ * the number kept before it, else to out[n-1-r], r being the number rejected
+ * before it -- kept elements first in input order, the rest after them in
+ * reverse input order.  Returns the number kept. */
+int64_t oracle_partition_u32(const uint32_t *a, uint32_t *out, int64_t n, int pred,
+                             int dtype, uint32_t thr)
+{
+    int64_t k = 0, r = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t x = a[i];
+        if (oracle_keep(x, pred, dtype, thr)) out[k++] = x;
+        else out[n - 1 - r++] = x;
+    }
+    return k;
+}

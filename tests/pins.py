@@ -225,6 +225,56 @@ def pin_f64(scan_f64) -> list:
     return fails
 
 
+def pin_partition(partition) -> list:
+    """partition(a, predicate, threshold) -> (out, k): kept elements first in
+    order, the rest after them in reverse order."""
+    fails = []
+    g = golden_io.load("partition_small.txt")
+    a = np.array(g["input"], dtype=np.int32)
+    rej = [0 if x != 0 else 1 for x in g["input"]]
+    if [sum(rej[:i]) for i in range(len(rej))] != g["rejected_positions"]:
+        fails.append("fixture rejection positions are not the exclusive scan of the rejections")
+    out, k = partition(a, "nonzero", 0)
+    _cmp("golden nonzero", out, g["nonzero_out"], fails)
+    if k != g["nonzero_kept_count"][0]:
+        fails.append("golden nonzero count")
+    out, k = partition(a, "greater", 2)
+    _cmp("golden > 2", out, g["greater_2_out"], fails)
+    if k != g["greater_2_kept_count"][0]:
+        fails.append("golden > 2 count")
+    # numpy masks: kept part in order, rejected part reversed, for every dtype
+    rng = np.random.default_rng(91)
+    for dt in (np.int32, np.uint32):
+        x = rng.integers(np.iinfo(dt).min, np.iinfo(dt).max, size=7001, dtype=np.int64, endpoint=True).astype(dt)
+        x[rng.random(x.size) < 0.4] = 0
+        thr = dt(rng.integers(np.iinfo(dt).min // 2, np.iinfo(dt).max // 2))
+        for pred, keep in (("nonzero", x != 0), ("greater", x > thr)):
+            out, k = partition(x, pred, thr if pred == "greater" else 0)
+            want = np.concatenate([x[keep], x[~keep][::-1]])
+            if k != int(keep.sum()) or not np.array_equal(np.asarray(out).view(np.uint32), want.view(np.uint32)):
+                fails.append("numpy mask %s %s" % (pred, np.dtype(dt).name))
+    f = rng.standard_normal(3001).astype(np.float32)
+    f[::89] = np.nan
+    keep = f > np.float32(-0.5)
+    out, k = partition(f, "greater", np.float32(-0.5))
+    want = np.concatenate([f[keep], f[~keep][::-1]])
+    if k != int(keep.sum()) or not np.array_equal(np.asarray(out).view(np.uint32), want.view(np.uint32)):
+        fails.append("numpy mask float32 (NaN rejected)")
+    # special cases: nothing kept (the input reversed), everything kept (a
+    # copy), empty input
+    o = np.arange(1, 101, dtype=np.int32)
+    out, k = partition(o, "greater", 1000)
+    if k != 0 or not np.array_equal(out, o[::-1]):
+        fails.append("nothing kept = reversed input")
+    out, k = partition(o, "greater", 0)
+    if k != 100 or not np.array_equal(out, o):
+        fails.append("everything kept = copy")
+    out, k = partition(np.zeros(0, dtype=np.int32), "nonzero", 0)
+    if k != 0 or np.asarray(out).size != 0:
+        fails.append("empty input")
+    return fails
+
+
 def pin_int_inplace(scan_int_out) -> list:
     """scan_int_out(a, exclusive, reverse, out) with out == a."""
     fails = []

@@ -311,3 +311,32 @@ def test_f64_tolerance_scale():
     ab = np.array([0.0, 1.0, 2.0**40])
     t = oracle.f64_tolerance(ab, 127)
     assert t[0] == 0.0 and np.allclose(t[1:], ab[1:] * 128 * 2.0**-53, rtol=1e-5)
+
+
+# ---------------------------------------------------------------- two-way partition
+
+def test_oracle_partition_pinned():
+    assert pins.pin_partition(oracle.partition) == []
+
+
+def _mp_rejected_in_order(a, pred, thr):
+    out, k = oracle.partition(a, pred, thr)
+    out = np.asarray(out).copy()
+    out[k:] = out[k:][::-1]
+    return out, k
+
+
+def _mp_swapped(a, pred, thr):
+    out, k = oracle.partition(a, pred, thr)
+    out = np.asarray(out)
+    return np.concatenate([out[k:][::-1], out[:k]]), out.size - k
+
+
+def _mp_off_by_one(a, pred, thr):
+    out, k = oracle.partition(a, pred, thr)
+    return np.roll(np.asarray(out), 1), k
+
+
+@pytest.mark.parametrize("mutant", [_mp_rejected_in_order, _mp_swapped, _mp_off_by_one])
+def test_pins_catch_partition_mutant(mutant):
+    assert pins.pin_partition(mutant) != []
