@@ -36,7 +36,9 @@ resident in HBM.  Prints ONE JSON line on stdout; progress goes to stderr.
              its recurrence y[i] = y[i-1] op x[i]
   compaction the same input read as int32, elements > 0 kept (about half)
              by the fused one-pass compaction, against torch's masked select
-             for context; the result must equal torch's
+             for context; the result must equal torch's.  Also the two-way
+             partition of the same input (kept first, the rest reversed after
+             them), whose halves must equal torch's masked selects
   wide       64-bit elements, n = 2^28: uint64 full-range values (the bench
              input as high halves, reversed as low halves) and float64
              normal(0,1), inclusive, kernel time from HIP events at 16 bytes
@@ -303,6 +305,16 @@ def compaction_run(scan, torch, x, y, stream):
            "fused_us": round(ms * 1e3, 1), "GBps_moved": round(moved / (ms * 1e-3) / 1e9, 1),
            "bytes_moved": int(moved), "torch_masked_select_us": round(ms_torch * 1e3, 1),
            "speedup_vs_torch": round(ms_torch / ms, 2), "results_equal_torch_masked_select": bool(ok)}
+    # two-way partition: every element written once (8 bytes per element)
+    z = torch.empty_like(x)
+    ms_p = timed(lambda: scan.partition_into(x, z, cnt, "greater", 0), 20)
+    kp = int(cnt.item())
+    keep = x > 0
+    ok_p = kp == k and bool(torch.equal(z[:kp], torch.masked_select(x, keep))) and \
+        bool(torch.equal(z[kp:], torch.masked_select(x, ~keep).flip(0)))
+    del z, keep
+    res.update({"partition_us": round(ms_p * 1e3, 1), "partition_GBps": round(8.0 * n / (ms_p * 1e-3) / 1e9, 1),
+                "partition_equal_torch": ok_p})
     log("compaction:", res)
     return res
 

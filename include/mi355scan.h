@@ -170,6 +170,20 @@ scan_status_t scan_compact(const void *in, void *out, int64_t n, scan_dtype_t dt
                            int32_t predicate, uint32_t threshold, int64_t *count,
                            hipStream_t stream);
 
+/* ---- two-way partition (one pass) ----
+ * The partitioning step of the Introduction (new offsets from a bitmap) with
+ * both sides kept: element i of in[0..n) goes to out[e_i] when the predicate
+ * keeps it (e_i = the number kept before i, as in scan_compact) and otherwise
+ * to out[n-1-r_i], r_i = i - e_i being the number rejected before it.  The
+ * kept elements fill out[0 .. *count) in input order, the rejected ones
+ * out[*count .. n) in reverse input order; every element is written once.
+ * predicate, threshold, count, n: as for scan_compact.  in and out must not
+ * overlap, in == out included (SCAN_ERROR_OVERLAP): rejected elements are
+ * written ahead of the data still to be read.  Uses the stream's workspace. */
+scan_status_t scan_partition(const void *in, void *out, int64_t n, scan_dtype_t dtype,
+                             int32_t predicate, uint32_t threshold, int64_t *count,
+                             hipStream_t stream);
+
 /* ---- float32 cumsum backward ----
  * For y = inclusive cumsum of x (per segment if offsets != NULL), the
  * gradient is the suffix sum of the upstream gradient:

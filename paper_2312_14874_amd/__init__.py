@@ -12,7 +12,7 @@ from .ops import (CumsumFn, LoopedScanGraph, SegmentedScanGraph, autotune,
                   cumsum_backward, exclusive_cumsum, force_config, num_configs,
                   reserve, segmented_scan, segmented_scan_looped,
                   selected_config, set_spin_limit, tune_load, tune_save, two_pass_cumsum,
-                  compact, compact_into)
+                  compact, compact_into, partition, partition_into)
 
 __all__ = [
     "SCAN_EXCLUSIVE", "SCAN_F32", "SCAN_I32", "SCAN_REVERSE", "SCAN_U32", "LIB_PATH",
@@ -20,5 +20,5 @@ __all__ = [
     "autotune", "check_device_error", "config_info", "cumsum", "cumsum_autograd",
     "cumsum_backward", "exclusive_cumsum", "force_config", "num_configs", "reserve",
     "segmented_scan", "segmented_scan_looped", "selected_config", "set_spin_limit",
-    "tune_load", "tune_save", "two_pass_cumsum", "compact", "compact_into",
+    "tune_load", "tune_save", "two_pass_cumsum", "compact", "compact_into", "partition", "partition_into",
 ]

@@ -45,6 +45,7 @@ SIGNATURES = {
     "scan_segmented_batch": (ST, [P, P, P, I32, I64, ST, U32, P]),
     "scan_two_pass": (ST, [P, P, I64, ST, U32, I32, I64, P]),
     "scan_compact": (ST, [P, P, I64, ST, I32, U32, P, P]),
+    "scan_partition": (ST, [P, P, I64, ST, I32, U32, P, P]),
     "scan_f32_backward": (ST, [P, P, I64, P, I32, P]),
     "scan_reserve": (ST, [I64, P]),
     "scan_release": (ST, [P]),

@@ -22,7 +22,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # feature, which is harmless.
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["scan_kernels.hip", "scan64_kernels.hip", "scan_api.cpp", "validate.cpp"]
+SOURCES = ["scan_kernels.hip", "scan64_kernels.hip", "partition_kernels.hip", "scan_api.cpp", "validate.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -6,6 +6,12 @@
 // kept before it) comes from the same decoupled look-back as the scan, and
 // the kept elements are written to their final places.  HBM traffic: 4 bytes
 // read per element plus 4 written per kept element.
+//
+// With PART the kernel is a two-way partition: in addition, an element that
+// is not kept goes to out[n-1-r], r being the number of rejected elements
+// before it (its index minus the number kept before it), so the rejected
+// elements fill the end of the output in reverse order and every element is
+// written once (8 bytes of traffic per element).
 #pragma once
 #include "scan_device.hpp"
 
@@ -27,7 +33,7 @@ __device__ __forceinline__ bool keep_element(uint32_t x, const CompactArgs &a) {
 // run (dword stores of consecutive lanes) instead of one scattered store per
 // element; as in scan_tiles, the registers a packed chunk frees take the next
 // tile's chunk at once.
-template <int BLOCK, int ITEMS, bool VEC, int MINW>
+template <int BLOCK, int ITEMS, bool VEC, int MINW, bool PART = false>
 __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
   using SH = Shape<BLOCK, ITEMS>;
   using Op = OpsU32;
@@ -111,6 +117,20 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
         (int)((ka.n - (int64_t)base) * 4 > 0x7fffffff ? 0x7fffffff : (ka.n - (int64_t)base) * 4), 0x00020000);
     uint32_t *stage = s_stage[wave];
     uint32_t cb = 0u;   // kept in the wave's chunks so far (uniform)
+    // partition: the wave's rejected elements go to out[rlo, rlo + rej) in
+    // reverse order, rlo = n - (rejected before the wave) - (rejected in it);
+    // a range outside [0, n) (only after a look-back that gave up) writes nothing
+    const int64_t wvalid64 = ka.n - wb;
+    const uint32_t wvalid = wvalid64 <= 0 ? 0u : (wvalid64 >= SH::WSPAN ? (uint32_t)SH::WSPAN : (uint32_t)wvalid64);
+    __amdgpu_buffer_rsrc_t rr = rs;
+    uint32_t rej = 0u, rc = 0u;   // rejected in the wave; in its chunks so far
+    if constexpr (PART) {
+      rej = wvalid - wsum;
+      const int64_t rlo = ka.n - (wb - (int64_t)base) - (int64_t)rej;
+      const bool ok = rlo >= 0 && rlo + (int64_t)rej <= ka.n;
+      rr = __builtin_amdgcn_make_buffer_rsrc(static_cast<uint32_t *>(ka.out) + (ok ? rlo : 0), (short)0,
+                                             ok ? (int)(4u * rej) : 0, 0x00020000);
+    }
     // chunk c: scan the lanes' counts, pack the kept elements into the
     // wave's LDS row (wave-private: no barrier; R[c] is free afterwards),
     // write them as one contiguous run
@@ -121,21 +141,45 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if ((m >> k) & 1u) stage[off + (uint32_t)__builtin_popcount(m & ((1u << k) - 1u))] = R[c][k];
-      return readlane32(x, 63);
+      const uint32_t kc = readlane32(x, 63);
+      if constexpr (PART) {
+        // rejected elements after the kept ones in the row: a valid element
+        // that is not kept has (4 lane + k) - (kept before it) rejected
+        // elements before it in the chunk
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (c * 256 + k < rem && !((m >> k) & 1u))
+            stage[kc + 4u * (uint32_t)lane + (uint32_t)k - off - (uint32_t)__builtin_popcount(m & ((1u << k) - 1u))] =
+                R[c][k];
+      }
+      return kc;
     };
-    auto flush = [&](const uint32_t kept) {
+    auto flush = [&](const int c, const uint32_t kept) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const uint32_t idx = 64u * j + lane;
         if (idx < kept) __builtin_amdgcn_raw_buffer_store_b32(stage[idx], rs, 4u * (cb + idx), 0, kNtAux);
       }
       cb += kept;
+      if constexpr (PART) {
+        // row entries [kept, valid) are the chunk's rejected elements in
+        // order; the i-th of the wave goes to out[rlo + rej - 1 - i]
+        const int64_t v64 = (int64_t)wvalid - 256 * c;
+        const uint32_t valid = v64 <= 0 ? 0u : (v64 >= 256 ? 256u : (uint32_t)v64);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t idx = 64u * j + lane;
+          if (idx >= kept && idx < valid)
+            __builtin_amdgcn_raw_buffer_store_b32(stage[idx], rr, 4u * (rej - 1u - (rc + idx - kept)), 0, kNtAux);
+        }
+        rc += valid - kept;
+      }
     };
     // the first half goes out while the next tile is taken from the counter,
     // then each chunk's registers take the next tile's chunk once it is packed
     constexpr int KH = SH::CH / 2;
 #pragma unroll
-    for (int c = 0; c < KH; ++c) flush(pack(c));
+    for (int c = 0; c < KH; ++c) flush(c, pack(c));
     int64_t next = ka.tiles;
     if (multi) {
       if (wave == 0) {
@@ -151,13 +195,13 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
       for (int c = KH; c < SH::CH; ++c) {
         const uint32_t kept = pack(c);
         in.load(c - KH, R[c - KH]);
-        flush(kept);
+        flush(c, kept);
       }
 #pragma unroll
       for (int c = SH::CH - KH; c < SH::CH; ++c) in.load(c, R[c]);
     } else {
 #pragma unroll
-      for (int c = KH; c < SH::CH; ++c) flush(pack(c));
+      for (int c = KH; c < SH::CH; ++c) flush(c, pack(c));
     }
     t = next;
   }

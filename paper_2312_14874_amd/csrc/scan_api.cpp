@@ -481,10 +481,13 @@ scan_status_t two_pass(const void *in, void *out, int64_t n, scan_dtype_t dt, ui
 
 // Stream compaction fused with the exclusive scan: one resident launch over
 // 16384-element tiles (tiles from the counter, as the scan's mode 1).
+// part: the two-way partition (rejected elements to the end, reversed), which
+// writes ahead of the tiles still to be read and so cannot run in place.
 scan_status_t compact(const void *in, void *out, int64_t n, scan_dtype_t dt, int32_t predicate,
-                      uint32_t threshold, int64_t *count, hipStream_t stream) {
+                      uint32_t threshold, int64_t *count, hipStream_t stream, bool part = false) {
   int r = check_dtype((int)dt);
   if (r == kOk) r = check_flat(in, out, n);
+  if (r == kOk && part && n > 0 && in == out) r = kOverlap;
   if (r != kOk) return st(r);
   if (!count || ((uintptr_t)count & 7u)) return SCAN_ERROR_INVALID_VALUE;
   if (predicate != SCAN_PRED_NONZERO && predicate != SCAN_PRED_GREATER) return SCAN_ERROR_INVALID_VALUE;
@@ -508,7 +511,7 @@ scan_status_t compact(const void *in, void *out, int64_t n, scan_dtype_t dt, int
     s = stream_ws(dev, stream, T, &ws);
     if (s != SCAN_SUCCESS) return s;
   }
-  const void *fn = K.tiles[((uintptr_t)in & 15u) == 0 ? 1 : 0];
+  const void *fn = (part ? kPartition : K).tiles[((uintptr_t)in & 15u) == 0 ? 1 : 0];
   const int64_t grid = std::min<int64_t>(T, resident_grid(fn, K.block, di.cus, 0, 100));
   CompactArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -759,6 +762,11 @@ scan_status_t scan_two_pass(const void *in, void *out, int64_t n, scan_dtype_t d
 scan_status_t scan_compact(const void *in, void *out, int64_t n, scan_dtype_t dtype, int32_t predicate,
                            uint32_t threshold, int64_t *count, hipStream_t stream) {
   return compact(in, out, n, dtype, predicate, threshold, count, stream);
+}
+
+scan_status_t scan_partition(const void *in, void *out, int64_t n, scan_dtype_t dtype, int32_t predicate,
+                             uint32_t threshold, int64_t *count, hipStream_t stream) {
+  return compact(in, out, n, dtype, predicate, threshold, count, stream, true);
 }
 
 scan_status_t scan_reserve(int64_t max_n, hipStream_t stream) {

@@ -54,6 +54,7 @@ struct CompactKernels {
   const void *set_count;   // writes the count when there is nothing to scan
 };
 extern const CompactKernels kCompact;
+extern const CompactKernels kPartition;   // two-way partition (set_count unused)
 
 // 64-bit scans (flat, forward, 16-byte aligned buffers): [0 = integer sum,
 // 1 = float64 sum].

@@ -118,11 +118,7 @@ def segmented_scan_looped(x: torch.Tensor, host_offsets, exclusive: bool = False
 PREDICATES = {"nonzero": SCAN_PRED_NONZERO, "greater": SCAN_PRED_GREATER}
 
 
-def compact_into(x: torch.Tensor, out: torch.Tensor, count: torch.Tensor, predicate: str = "nonzero",
-                 threshold=0) -> None:
-    """Asynchronous stream compaction: out[:count] receives, in order, the
-    elements of x the predicate keeps ("nonzero", or "greater": x > threshold
-    in x's type); count is a one-element int64 GPU tensor."""
+def _select_args(x, out, count, predicate, threshold):
     if predicate not in PREDICATES:
         raise ValueError("predicate must be one of %s" % sorted(PREDICATES))
     dt = _check_tensor(x, "x")
@@ -130,9 +126,38 @@ def compact_into(x: torch.Tensor, out: torch.Tensor, count: torch.Tensor, predic
     if count.dtype != torch.int64 or count.numel() != 1 or count.device != x.device:
         raise ValueError("count must be a one-element int64 tensor on x's device")
     thr = torch.tensor([threshold], dtype=x.dtype).view(torch.int32).item() & 0xFFFFFFFF
+    return dt, out, thr
+
+
+def compact_into(x: torch.Tensor, out: torch.Tensor, count: torch.Tensor, predicate: str = "nonzero",
+                 threshold=0) -> None:
+    """Asynchronous stream compaction: out[:count] receives, in order, the
+    elements of x the predicate keeps ("nonzero", or "greater": x > threshold
+    in x's type); count is a one-element int64 GPU tensor."""
+    dt, out, thr = _select_args(x, out, count, predicate, threshold)
     with torch.cuda.device(x.device):
         check(lib.scan_compact(x.data_ptr(), out.data_ptr(), x.numel(), dt, PREDICATES[predicate], thr,
                                count.data_ptr(), _stream(x.device)), "scan_compact")
+
+
+def partition_into(x: torch.Tensor, out: torch.Tensor, count: torch.Tensor, predicate: str = "nonzero",
+                   threshold=0) -> None:
+    """Asynchronous two-way partition: out[:count] receives the elements of x
+    the predicate keeps, in order, and out[count:] the others in reverse
+    order; out must not overlap x."""
+    dt, out, thr = _select_args(x, out, count, predicate, threshold)
+    with torch.cuda.device(x.device):
+        check(lib.scan_partition(x.data_ptr(), out.data_ptr(), x.numel(), dt, PREDICATES[predicate], thr,
+                                 count.data_ptr(), _stream(x.device)), "scan_partition")
+
+
+def partition(x: torch.Tensor, predicate: str = "nonzero", threshold=0):
+    """(out, k): the kept elements of x in out[:k] in order, the others in
+    out[k:] in reverse order (synchronises to read k)."""
+    out = torch.empty_like(x)
+    count = torch.empty(1, dtype=torch.int64, device=x.device)
+    partition_into(x, out, count, predicate, threshold)
+    return out, int(count.item())
 
 
 def compact(x: torch.Tensor, predicate: str = "nonzero", threshold=0) -> torch.Tensor:

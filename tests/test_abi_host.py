@@ -107,6 +107,17 @@ def test_compact_argument_errors():
     assert f(1 << 40, 1 << 41, 1 << 33, 0, 0, 0, 16, None) == NOT_SUPPORTED   # n >= 2^32
 
 
+def test_partition_argument_errors():
+    L = _lib()
+    f = L.lib.scan_partition
+    assert f(4096, 8192, 10, 0, 0, 0, None, None) == INVALID        # no count pointer
+    assert f(4096, 8192, 10, 0, 2, 0, 16, None) == INVALID          # unknown predicate
+    assert f(4096, 4096, 10, 0, 0, 0, 16, None) == OVERLAP          # in place is refused
+    assert f(4096, 4100, 10, 0, 0, 0, 16, None) == OVERLAP
+    assert f(4096, 8192, 10, 3, 0, 0, 16, None) == NOT_SUPPORTED    # 64-bit dtypes
+    assert f(1 << 40, 1 << 41, 1 << 33, 0, 0, 0, 16, None) == NOT_SUPPORTED   # n >= 2^32
+
+
 def test_two_pass_argument_errors():
     L = _lib()
     f = L.lib.scan_two_pass
