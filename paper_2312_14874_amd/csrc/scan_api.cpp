@@ -497,11 +497,12 @@ scan_status_t compact(const void *in, void *out, int64_t n, scan_dtype_t dt, int
   DeviceInfo di;
   scan_status_t s = current_device(&dev, &di);
   if (s != SCAN_SUCCESS) return s;
-  const CompactKernels &K = kCompact;
+  // the partition kernels have their own shape; the n = 0 count kernel is the compaction's
+  const CompactKernels &K = part ? kPartition : kCompact;
   if (n == 0) {
     int64_t zero = 0;
     void *zargs[] = {&count, &zero};
-    hipError_t e = hipLaunchKernel(K.set_count, dim3(1), dim3(1), zargs, 0, stream);
+    hipError_t e = hipLaunchKernel(kCompact.set_count, dim3(1), dim3(1), zargs, 0, stream);
     return e == hipSuccess ? SCAN_SUCCESS : hip_fail(e);
   }
   const int64_t tile = (int64_t)K.block * K.items;
@@ -511,7 +512,7 @@ scan_status_t compact(const void *in, void *out, int64_t n, scan_dtype_t dt, int
     s = stream_ws(dev, stream, T, &ws);
     if (s != SCAN_SUCCESS) return s;
   }
-  const void *fn = (part ? kPartition : K).tiles[((uintptr_t)in & 15u) == 0 ? 1 : 0];
+  const void *fn = K.tiles[((uintptr_t)in & 15u) == 0 ? 1 : 0];
   const int64_t grid = std::min<int64_t>(T, resident_grid(fn, K.block, di.cus, 0, 100));
   CompactArgs a;
   std::memset(&a, 0, sizeof(a));
