@@ -7,7 +7,8 @@
  * and the exclusive scan writes the identity (0) first and drops the last
  * inclusive value:  out[0] = 0, out[i] = a[0] + ... + a[i-1].
  * Section 2 (thread-level parallelism) allows the result to replace the input:
- * in == out is legal everywhere below (in place); any other overlap is an error.
+ * in == out is legal everywhere below (in place) except for scan_partition;
+ * any other overlap is an error.
  *
  * The GPU method is the device-scale form of the paper's cache-friendly
  * two-pass scheme (Section 2.2): every tile of the input is loaded once into
@@ -17,13 +18,15 @@
  * which each tile waits only on its predecessors (the adjacent-only
  * synchronisation that Section 2.2.1 suggests in place of a central barrier).
  * HBM traffic is therefore the two-words-per-element floor: 8 bytes per
- * element for every entry point, plus 8 bytes per tile of status.
+ * element for every 32-bit scan (16 for 64-bit elements), plus 8 bytes per
+ * tile of status (16 for 64-bit elements).
  *
  * Conventions for every function:
  *  - Pointers named in/out/grad_* and offsets are DEVICE pointers owned by the
  *    caller; they must stay valid until the work enqueued on `stream`
- *    completes.  Elements need 4-byte alignment, offsets 8-byte alignment;
- *    16-byte aligned buffers take the vector fast path automatically.
+ *    completes.  32-bit elements need 4-byte alignment, offsets 8-byte
+ *    alignment; 16-byte aligned buffers take the vector fast path
+ *    automatically.  64-bit elements need 16-byte aligned buffers.
  *  - All functions are asynchronous on `stream` (a hipStream_t; 0 = the null
  *    stream) and do not synchronise the host, except where a workspace has to
  *    grow (see scan_reserve).
@@ -34,7 +37,8 @@
  *  - No function aborts or throws across the ABI; a failing HIP call is
  *    reported as SCAN_ERROR_LAUNCH / SCAN_ERROR_OUT_OF_MEMORY and its hipError_t
  *    is kept for scan_last_hip_error().
- *  - Integer scans wrap modulo 2^32; int32 and uint32 give identical bits.
+ *  - Integer scans wrap modulo 2^32 (2^64 for 64-bit elements); signed and
+ *    unsigned types of one width give identical bits.
  *  - float32 scans: the result is within 2^-20 * sum_{j<=i} |a_j| of the exact
  *    prefix sum (sum_{j<i} for exclusive).  The paper notes that parallel float
  *    sums may differ slightly from sequential ones; this library fixes the
