@@ -56,11 +56,11 @@ def _load():
         lib.oracle_segmented_op_u32.argtypes = [P, P, P, I64, I, I, I, I]
         lib.oracle_compact_u32.argtypes = [P, P, I64, I, I, ctypes.c_uint32]
         lib.oracle_compact_u32.restype = I64
-        lib.oracle_scan_u64.argtypes = [P, P, I64, I]
+        lib.oracle_scan_u64.argtypes = [P, P, I64, I, I]
         lib.oracle_scan_u64.restype = None
         lib.oracle_partition_u32.argtypes = [P, P, I64, I, I, ctypes.c_uint32]
         lib.oracle_partition_u32.restype = I64
-        lib.oracle_scan_f64.argtypes = [P, P, P, I64, I]
+        lib.oracle_scan_f64.argtypes = [P, P, P, I64, I, I]
         lib.oracle_scan_f64.restype = None
         for f in (lib.oracle_scan_u32, lib.oracle_scan_f32_f64,
                   lib.oracle_segmented_u32, lib.oracle_segmented_f32_f64,
@@ -94,8 +94,9 @@ def scan_int(a: np.ndarray, exclusive: bool = False, reverse: bool = False,
     return dst.view(np.asarray(a).dtype)
 
 
-def scan_int64(a: np.ndarray, exclusive: bool = False, out: np.ndarray | None = None) -> np.ndarray:
-    """Forward scan of 64-bit integers, wrapping modulo 2^64.
+def scan_int64(a: np.ndarray, exclusive: bool = False, out: np.ndarray | None = None,
+               reverse: bool = False) -> np.ndarray:
+    """Scan of 64-bit integers, wrapping modulo 2^64 (reverse: suffix scan).
 
     Returns an array of a's dtype (int64 or uint64); ``out`` may be ``a``.
     """
@@ -104,13 +105,13 @@ def scan_int64(a: np.ndarray, exclusive: bool = False, out: np.ndarray | None = 
         raise TypeError("64-bit oracle takes int64/uint64, got %s" % a.dtype)
     src = a.view(np.uint64)
     dst = np.empty_like(src) if out is None else out.view(np.uint64)
-    _load().oracle_scan_u64(_ptr(src), _ptr(dst), src.size, int(exclusive))
+    _load().oracle_scan_u64(_ptr(src), _ptr(dst), src.size, int(exclusive), int(reverse))
     return dst.view(a.dtype)
 
 
-def scan_f64(a: np.ndarray, exclusive: bool = False, with_abs: bool = True):
-    """Forward prefix sums of float64 input, accumulated in double-double and
-    rounded once to float64.
+def scan_f64(a: np.ndarray, exclusive: bool = False, with_abs: bool = True, reverse: bool = False):
+    """Prefix sums (reverse: suffix sums) of float64 input, accumulated in
+    double-double and rounded once to float64.
 
     Returns (sums, abs_sums): float64 arrays; abs_sums[i] is the running sum
     of |a| (the scale of the error tolerance), or None if ``with_abs`` is False.
@@ -118,7 +119,7 @@ def scan_f64(a: np.ndarray, exclusive: bool = False, with_abs: bool = True):
     src = np.ascontiguousarray(a, dtype=np.float64)
     s = np.empty(src.size, dtype=np.float64)
     ab = np.empty(src.size, dtype=np.float64) if with_abs else None
-    _load().oracle_scan_f64(_ptr(src), _ptr(s), _ptr(ab), src.size, int(exclusive))
+    _load().oracle_scan_f64(_ptr(src), _ptr(s), _ptr(ab), src.size, int(exclusive), int(reverse))
     return s, ab
 
 

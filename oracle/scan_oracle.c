@@ -118,11 +118,13 @@ void oracle_scan_u32(const uint32_t *a, uint32_t *out, int64_t n,
 }
 
 /* 64-bit integers: the same pass in uint64_t, modulo 2^64 (int64 data is the
- * same bit pattern).  Forward only. */
-void oracle_scan_u64(const uint64_t *a, uint64_t *out, int64_t n, int exclusive)
+ * same bit pattern); reverse runs it from the last element down. */
+void oracle_scan_u64(const uint64_t *a, uint64_t *out, int64_t n, int exclusive, int reverse)
 {
     uint64_t acc = 0u;
-    for (int64_t i = 0; i < n; ++i) {
+    int64_t i = reverse ? n - 1 : 0;
+    const int64_t step = reverse ? -1 : 1;
+    for (int64_t k = 0; k < n; ++k, i += step) {
         uint64_t x = a[i];
         if (exclusive) { out[i] = acc; acc += x; }
         else           { acc += x; out[i] = acc; }
@@ -136,8 +138,8 @@ void oracle_scan_u64(const uint64_t *a, uint64_t *out, int64_t n, int exclusive)
  * and the pair is renormalised (Dekker's Fast2Sum), so hi is the total
  * rounded to float64 and the accumulated error stays near n * 2^-106 *
  * sum|a|, far below one float64 rounding.  abs_out[i] (may be NULL): the
- * plain float64 running sum of |a|, the scale of the tolerance.  Forward
- * only. */
+ * plain float64 running sum of |a|, the scale of the tolerance.  Reverse
+ * runs the pass from the last element down (suffix sums). */
 static void two_sum(double a, double b, double *s, double *e)
 {
     double x = a + b;
@@ -147,10 +149,13 @@ static void two_sum(double a, double b, double *s, double *e)
     *e = (a - av) + (b - bv);
 }
 
-void oracle_scan_f64(const double *a, double *out, double *abs_out, int64_t n, int exclusive)
+void oracle_scan_f64(const double *a, double *out, double *abs_out, int64_t n, int exclusive,
+                     int reverse)
 {
     double hi = 0.0, lo = 0.0, aacc = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
+    int64_t i = reverse ? n - 1 : 0;
+    const int64_t step = reverse ? -1 : 1;
+    for (int64_t k = 0; k < n; ++k, i += step) {
         double x = a[i];
         if (exclusive) {
             out[i] = hi;

@@ -128,12 +128,14 @@ def _cmp64(name, got, want, fails):
 
 
 def pin_int64(scan64) -> list:
-    """scan64(a, exclusive) -> array: forward scan wrapping modulo 2^64."""
+    """scan64(a, exclusive, reverse) -> array: scan wrapping modulo 2^64."""
     fails = []
     g = golden_io.load("wrap_u64.txt")
     a = np.array(g["input"], dtype=np.uint64)
-    _cmp64("golden inclusive", scan64(a, False), g["inclusive"], fails)
-    _cmp64("golden exclusive", scan64(a, True), g["exclusive"], fails)
+    _cmp64("golden inclusive", scan64(a, False, False), g["inclusive"], fails)
+    _cmp64("golden exclusive", scan64(a, True, False), g["exclusive"], fails)
+    _cmp64("golden reverse inclusive", scan64(a, False, True), g["reverse_inclusive"], fails)
+    _cmp64("golden reverse exclusive", scan64(a, True, True), g["reverse_exclusive"], fails)
 
     # closed form: a_i = c + d*i (mod 2^64) -> (i+1)c + d*i(i+1)/2, with values
     # that carry out of the low 32 bits at every step and wrap past 2^64
@@ -141,9 +143,9 @@ def pin_int64(scan64) -> list:
     n = 20000
     a = np.array([(c + d * k) % M64 for k in range(n)], dtype=np.uint64)
     want = [((k + 1) * c + d * k * (k + 1) // 2) % M64 for k in range(n)]
-    _cmp64("arithmetic progression inclusive", scan64(a, False), want, fails)
+    _cmp64("arithmetic progression inclusive", scan64(a, False, False), want, fails)
     want_ex = [(k * c + d * (k - 1) * k // 2) % M64 for k in range(n)]
-    _cmp64("arithmetic progression exclusive", scan64(a, True), want_ex, fails)
+    _cmp64("arithmetic progression exclusive", scan64(a, True, False), want_ex, fails)
 
     # brute force from the definition in Python integers
     rng = np.random.default_rng(11)
@@ -152,14 +154,19 @@ def pin_int64(scan64) -> list:
         v = [int(x) for x in a]
         for ex in (False, True):
             want = [sum(v[:i] if ex else v[:i + 1]) for i in range(n)]
-            _cmp64("brute n=%d ex=%d" % (n, ex), scan64(a, ex), want, fails)
+            _cmp64("brute n=%d ex=%d" % (n, ex), scan64(a, ex, False), want, fails)
+            want = [sum(v[i + 1:] if ex else v[i:]) for i in range(n)]
+            _cmp64("brute reverse n=%d ex=%d" % (n, ex), scan64(a, ex, True), want, fails)
 
     # numpy's wrapping uint64 cumsum
     a = rng.integers(0, M64, size=100_003, dtype=np.uint64)
-    inc = np.asarray(scan64(a, False)).view(np.uint64)
-    exc = np.asarray(scan64(a, True)).view(np.uint64)
+    inc = np.asarray(scan64(a, False, False)).view(np.uint64)
+    exc = np.asarray(scan64(a, True, False)).view(np.uint64)
     if not np.array_equal(inc, np.cumsum(a, dtype=np.uint64)):
         fails.append("numpy cumsum uint64")
+    if not np.array_equal(np.asarray(scan64(a, False, True)).view(np.uint64),
+                          np.cumsum(a[::-1], dtype=np.uint64)[::-1]):
+        fails.append("numpy flipped cumsum uint64")
     # invariants: inclusive - exclusive = input; the low 32 bits are the
     # 32-bit scan of the low halves
     if not np.array_equal(inc - exc, a):
@@ -169,37 +176,40 @@ def pin_int64(scan64) -> list:
         fails.append("low halves differ from the 32-bit scan")
     # signed view: negative int64 input, the same bits as uint64
     neg = -np.arange(1, 1001, dtype=np.int64)
-    s = np.asarray(scan64(neg, False))
+    s = np.asarray(scan64(neg, False, False))
     if s.dtype != np.int64 or [int(x) for x in s] != [-(k + 1) * (k + 2) // 2 for k in range(1000)]:
         fails.append("int64 negative input")
     return fails
 
 
 def pin_f64(scan_f64) -> list:
-    """scan_f64(a, exclusive) -> (sums float64, abs_sums float64): the exact
-    prefix sums rounded to float64."""
+    """scan_f64(a, exclusive, reverse) -> (sums float64, abs_sums float64):
+    the exact prefix (reverse: suffix) sums rounded to float64."""
     fails = []
     g = golden_io.load("cancel_f64.txt", conv=float)
     a = np.array(g["input"], dtype=np.float64)
-    s, _ = scan_f64(a, False)
-    _fcmp("golden cancel inclusive", s, g["inclusive"], fails)
-    s, _ = scan_f64(a, True)
-    _fcmp("golden cancel exclusive", s, g["exclusive"], fails)
+    for key, ex, rev in (("inclusive", False, False), ("exclusive", True, False),
+                         ("reverse_inclusive", False, True), ("reverse_exclusive", True, True)):
+        s, _ = scan_f64(a, ex, rev)
+        _fcmp("golden cancel " + key, s, g[key], fails)
 
     # closed form: a_i = i (integers below 2^26: every partial sum exact)
     n = 60_000
     a = np.arange(n, dtype=np.float64)
     k = np.arange(n, dtype=np.int64)
-    s, ab = scan_f64(a, False)
+    s, ab = scan_f64(a, False, False)
     _fcmp("arithmetic progression inclusive", s, k * (k + 1) // 2, fails)
     _fcmp("abs of a nonnegative input", ab, k * (k + 1) // 2, fails)
-    s, _ = scan_f64(a, True)
+    s, _ = scan_f64(a, True, False)
     _fcmp("arithmetic progression exclusive", s, (k - 1) * k // 2, fails)
+    s, _ = scan_f64(a, False, True)
+    tot = (n - 1) * n // 2
+    _fcmp("arithmetic progression reverse", s, tot - (k - 1) * k // 2, fails)
 
     # exact rational prefix sums, rounded once, over a wide exponent range
     rng = np.random.default_rng(19)
     a = rng.standard_normal(400) * np.ldexp(1.0, rng.integers(-30, 30, size=400))
-    s, ab = scan_f64(a, False)
+    s, ab = scan_f64(a, False, False)
     acc = Fraction(0)
     for i, x in enumerate(a):
         acc += Fraction(float(x))
@@ -210,14 +220,20 @@ def pin_f64(scan_f64) -> list:
             break
     # math.fsum (correctly rounded sum of floats) at sampled prefixes
     a = rng.standard_normal(200_001) * 1e3
-    s, ab = scan_f64(a, False)
+    s, ab = scan_f64(a, False, False)
     for i in list(range(0, a.size, 9_973)) + [a.size - 1]:
         want = math.fsum(a[:i + 1].tolist())
         if abs(float(s[i]) - want) > math.ulp(want) / 2 + 2.0**-95 * float(ab[i]):
             fails.append("fsum prefix at %d" % i)
             break
+    r, rab = scan_f64(a, False, True)
+    for i in [0] + list(range(7, a.size, 11_113)):
+        want = math.fsum(a[i:].tolist())
+        if abs(float(r[i]) - want) > math.ulp(want) / 2 + 2.0**-95 * float(rab[i]):
+            fails.append("fsum suffix at %d" % i)
+            break
     # exclusive is the inclusive result shifted by one, identity first
-    e, eab = scan_f64(a, True)
+    e, eab = scan_f64(a, True, False)
     if e[0] != 0.0 or not np.array_equal(e[1:], s[:-1]):
         fails.append("exclusive != shifted inclusive")
     if abs(float(ab[-1]) - math.fsum(np.abs(a).tolist())) > a.size * 2.0**-53 * float(ab[-1]):

@@ -223,28 +223,34 @@ def test_pins_catch_operator_mutant(mutant):
 # ---------------------------------------------------------------- 64-bit integers
 
 def test_oracle_int64_pinned():
-    assert pins.pin_int64(lambda a, ex: oracle.scan_int64(a, exclusive=ex)) == []
+    assert pins.pin_int64(lambda a, ex, rev: oracle.scan_int64(a, exclusive=ex, reverse=rev)) == []
 
 
-def _m64_split_halves(a, ex):
+def _m64_split_halves(a, ex, rev):
     # scans the two 32-bit halves separately: the carry out of the low half is lost
     v = np.ascontiguousarray(a).view(np.uint64)
-    lo = np.asarray(oracle.scan_int((v & np.uint64(0xFFFFFFFF)).astype(np.uint32), exclusive=ex)).astype(np.uint64)
-    hi = np.asarray(oracle.scan_int((v >> np.uint64(32)).astype(np.uint32), exclusive=ex)).astype(np.uint64)
+    lo = np.asarray(oracle.scan_int((v & np.uint64(0xFFFFFFFF)).astype(np.uint32), exclusive=ex,
+                                    reverse=rev)).astype(np.uint64)
+    hi = np.asarray(oracle.scan_int((v >> np.uint64(32)).astype(np.uint32), exclusive=ex,
+                                    reverse=rev)).astype(np.uint64)
     return ((hi << np.uint64(32)) | lo).view(np.asarray(a).dtype)
 
 
-def _m64_float_accumulator(a, ex):
+def _m64_float_accumulator(a, ex, rev):
     v = np.ascontiguousarray(a).view(np.uint64).astype(np.float64)
     c = np.cumsum(v) - (v if ex else 0)
     return np.mod(c, 2.0**64).astype(np.uint64).view(np.asarray(a).dtype)
 
 
-def _m64_exclusive_is_inclusive(a, ex):
-    return oracle.scan_int64(a, exclusive=False)
+def _m64_exclusive_is_inclusive(a, ex, rev):
+    return oracle.scan_int64(a, exclusive=False, reverse=rev)
 
 
-def _m64_no_wrap_signed(a, ex):
+def _m64_reverse_ignored(a, ex, rev):
+    return oracle.scan_int64(a, exclusive=ex)
+
+
+def _m64_no_wrap_signed(a, ex, rev):
     # accumulates in signed 64 bits saturating at the int64 range
     v = [int(x) for x in np.ascontiguousarray(a).view(np.int64)]
     out, acc = [], 0
@@ -259,7 +265,7 @@ def _m64_no_wrap_signed(a, ex):
 
 
 @pytest.mark.parametrize("mutant", [_m64_split_halves, _m64_float_accumulator, _m64_exclusive_is_inclusive,
-                                    _m64_no_wrap_signed])
+                                    _m64_no_wrap_signed, _m64_reverse_ignored])
 def test_pins_catch_int64_mutant(mutant):
     assert pins.pin_int64(mutant) != []
 
@@ -267,10 +273,10 @@ def test_pins_catch_int64_mutant(mutant):
 # ---------------------------------------------------------------- float64
 
 def test_oracle_f64_pinned():
-    assert pins.pin_f64(lambda a, ex: oracle.scan_f64(a, exclusive=ex)) == []
+    assert pins.pin_f64(lambda a, ex, rev: oracle.scan_f64(a, exclusive=ex, reverse=rev)) == []
 
 
-def _mf64_naive(a, ex):
+def _mf64_naive(a, ex, rev):
     # plain left-to-right float64 accumulation: loses the cancellation
     v = np.asarray(a, dtype=np.float64)
     c = np.add.accumulate(v)
@@ -281,7 +287,7 @@ def _mf64_naive(a, ex):
     return c, ab
 
 
-def _mf64_f32_accumulator(a, ex):
+def _mf64_f32_accumulator(a, ex, rev):
     v = np.asarray(a, dtype=np.float64)
     c = np.cumsum(v.astype(np.float32), dtype=np.float32).astype(np.float64)
     _, ab = oracle.scan_f64(a, exclusive=ex)
@@ -290,19 +296,23 @@ def _mf64_f32_accumulator(a, ex):
     return c, ab
 
 
-def _mf64_exclusive_is_inclusive(a, ex):
-    return oracle.scan_f64(a, exclusive=False)
+def _mf64_exclusive_is_inclusive(a, ex, rev):
+    return oracle.scan_f64(a, exclusive=False, reverse=rev)
 
 
-def _mf64_dropped_first(a, ex):
+def _mf64_reverse_ignored(a, ex, rev):
+    return oracle.scan_f64(a, exclusive=ex)
+
+
+def _mf64_dropped_first(a, ex, rev):
     v = np.asarray(a, dtype=np.float64).copy()
     if v.size:
         v[0] = 0.0
-    return oracle.scan_f64(v, exclusive=ex)
+    return oracle.scan_f64(v, exclusive=ex, reverse=rev)
 
 
 @pytest.mark.parametrize("mutant", [_mf64_naive, _mf64_f32_accumulator, _mf64_exclusive_is_inclusive,
-                                    _mf64_dropped_first])
+                                    _mf64_dropped_first, _mf64_reverse_ignored])
 def test_pins_catch_f64_mutant(mutant):
     assert pins.pin_f64(mutant) != []
 
