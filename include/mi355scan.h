@@ -107,7 +107,7 @@ scan_status_t scan_exclusive_f32(const float *in, float *out, int64_t n, hipStre
  * SCAN_I64 / SCAN_U64 / SCAN_F64 (the Introduction's scan with + on 64-bit
  * elements, e.g. offsets past 2^32 or float64 data): in and out must be
  * 16-byte aligned (SCAN_ERROR_INVALID_VALUE otherwise), flags SCAN_EXCLUSIVE
- * only (SCAN_REVERSE or an operator: SCAN_ERROR_NOT_SUPPORTED).  Integers are
+ * and SCAN_REVERSE (an operator: SCAN_ERROR_NOT_SUPPORTED).  Integers are
  * bit-exact, wrapping modulo 2^64; a float64 result is a sum of the same
  * inputs in another association, within (8 * tiles + 128) * 2^-53 times the
  * running sum of |a| of the exact prefix sum (tiles = ceil(n / 32768); the

@@ -6,8 +6,10 @@
 // only when both halves carry the same flag (flags only move forward, EMPTY
 // -> AGG -> PREFIX, so a pair with different flags is a publication in
 // progress and reads as EMPTY), so no fences are needed.  A lane holds two
-// elements per 16-byte load; a chunk is 128 elements.  Flat forward scans,
-// inclusive or exclusive.
+// elements per 16-byte load; a chunk is 128 elements.  Flat scans, inclusive
+// or exclusive, forward or reverse: a reverse scan walks the same physical
+// tiles, wave spans, chunks, lanes and element pairs from the top down, so
+// every step above works on the logical (reversed) order unchanged.
 #pragma once
 #include "scan_device.hpp"
 
@@ -147,11 +149,13 @@ __device__ uint64_t look_back64(const uint64_t *st, int64_t t, uint32_t spin_lim
   }
 }
 
-// One wave's span of tile t in an 8-byte-element buffer: 16-byte loads and
-// stores, lane l of chunk c at byte 1024c + 16l; the buffer resource's
-// record count returns 0 beyond n and drops stores there.
-template <int WSPAN>
+// One wave's span in an 8-byte-element buffer, starting at element wb: 16-byte
+// loads and stores, lane l of chunk c at byte 1024c + 16l (REV: lane 63-l of
+// chunk CH-1-c); the buffer resource's record count returns 0 beyond n and
+// drops stores there.
+template <int WSPAN, bool REV>
 struct WaveSpan64 {
+  static constexpr int CH = WSPAN / 128;
   __amdgpu_buffer_rsrc_t rs;
   uint32_t lo;
   __device__ __forceinline__ WaveSpan64(const void *buf, int64_t n, int64_t wb) {
@@ -159,13 +163,15 @@ struct WaveSpan64 {
     const int nr = valid <= 0 ? 0 : (valid >= 8 * WSPAN ? 8 * WSPAN : (int)valid);
     rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint64_t *>(static_cast<const uint64_t *>(buf)) + wb,
                                            (short)0, nr, 0x00020000);
-    lo = 16u * (opaque_tid() & 63u);
+    const uint32_t l = opaque_tid() & 63u;
+    lo = 16u * (REV ? 63u - l : l);
   }
+  static __device__ __forceinline__ uint32_t chunk(int c) { return 1024u * (uint32_t)(REV ? CH - 1 - c : c); }
   __device__ __forceinline__ void load(int c, u32x4 &r) const {
-    r = __builtin_amdgcn_raw_buffer_load_b128(rs, lo + 1024u * (uint32_t)c, 0, kNtAux);
+    r = __builtin_amdgcn_raw_buffer_load_b128(rs, lo + chunk(c), 0, kNtAux);
   }
   __device__ __forceinline__ void store(int c, const u32x4 &r) const {
-    __builtin_amdgcn_raw_buffer_store_b128(r, rs, lo + 1024u * (uint32_t)c, 0, kNtAux);
+    __builtin_amdgcn_raw_buffer_store_b128(r, rs, lo + chunk(c), 0, kNtAux);
   }
 };
 
@@ -173,13 +179,17 @@ __device__ __forceinline__ uint64_t u64_of(uint32_t lo, uint32_t hi) { return ((
 
 // Resident grid, tiles from the device counter; ITEMS elements per thread
 // (2 per chunk and lane), the wave's span WSPAN = 64 * ITEMS elements.
-template <class Op, int BLOCK, int ITEMS, int MINW>
+template <class Op, int BLOCK, int ITEMS, int MINW, bool REV>
 __global__ void __launch_bounds__(BLOCK, MINW) scan64_tiles(KernelArgs a) {
   static_assert(ITEMS % 2 == 0, "two elements per 16-byte group");
   constexpr int WAVES = BLOCK / 64;
   constexpr int CH = ITEMS / 2;
   constexpr int WSPAN = 64 * ITEMS;
   constexpr int64_t TILE = (int64_t)BLOCK * ITEMS;
+  using Span = WaveSpan64<WSPAN, REV>;
+  // element k (0 = first in logical order) of a lane's 16-byte pair: dwords
+  // 2k, 2k+1 forward, 2(1-k), 2(1-k)+1 reverse
+  constexpr int E0 = REV ? 2 : 0, E1 = REV ? 0 : 2;
   __shared__ uint64_t s_wtot[WAVES];
   __shared__ uint64_t s_carry;
   __shared__ int64_t s_tile;
@@ -187,6 +197,12 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan64_tiles(KernelArgs a) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = wave_id();
+  // first element of logical tile t's span for this wave (REV: physical tile
+  // tiles-1-t, wave spans from the top)
+  const auto span_base = [&](int64_t t) -> int64_t {
+    const int64_t pt = REV ? a.tiles - 1 - t : t;
+    return pt * TILE + (int64_t)(REV ? WAVES - 1 - wave : wave) * WSPAN;
+  };
   const bool multi = a.tiles > 1;
   const bool ex = a.exclusive != 0u;
   uint32_t parity = 0;
@@ -206,7 +222,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan64_tiles(KernelArgs a) {
   }
   u32x4 R[CH];
   if (t < a.tiles) {
-    const WaveSpan64<WSPAN> in(a.in, a.n, t * TILE + (int64_t)wave * WSPAN);
+    const Span in(a.in, a.n, span_base(t));
 #pragma unroll
     for (int c = 0; c < CH; ++c) in.load(c, R[c]);
   }
@@ -215,17 +231,17 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan64_tiles(KernelArgs a) {
     uint64_t wsum = 0;
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      const uint64_t x0 = u64_of(R[c][0], R[c][1]);
-      const uint64_t x1 = Op::add(u64_of(R[c][2], R[c][3]), x0);
+      const uint64_t x0 = u64_of(R[c][E0], R[c][E0 + 1]);
+      const uint64_t x1 = Op::add(u64_of(R[c][E1], R[c][E1 + 1]), x0);
       const uint64_t x = Op::wave_scan(x1);
       const uint64_t up = lane_up1_64(x);
       const uint64_t off = c > 0 ? Op::add(up, wsum) : up;
       const uint64_t o0 = ex ? off : Op::add(off, x0);
       const uint64_t o1 = ex ? Op::add(off, x0) : Op::add(off, x1);
-      R[c][0] = (uint32_t)o0;
-      R[c][1] = (uint32_t)(o0 >> 32);
-      R[c][2] = (uint32_t)o1;
-      R[c][3] = (uint32_t)(o1 >> 32);
+      R[c][E0] = (uint32_t)o0;
+      R[c][E0 + 1] = (uint32_t)(o0 >> 32);
+      R[c][E1] = (uint32_t)o1;
+      R[c][E1 + 1] = (uint32_t)(o1 >> 32);
       wsum = c > 0 ? Op::add(wsum, readlane64(x, 63)) : readlane64(x, 63);
       asm volatile("" : "+v"(R[c]));
     }
@@ -252,7 +268,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan64_tiles(KernelArgs a) {
     }
     __syncthreads();
     const uint64_t win = t > 0 ? Op::add(s_carry, wpre) : wpre;
-    const WaveSpan64<WSPAN> out(a.out, a.n, t * TILE + (int64_t)wave * WSPAN);
+    const Span out(a.out, a.n, span_base(t));
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       const uint64_t o0 = Op::add(u64_of(R[c][0], R[c][1]), win), o1 = Op::add(u64_of(R[c][2], R[c][3]), win);
@@ -276,7 +292,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan64_tiles(KernelArgs a) {
       next = s_tile;
     }
     if (next < a.tiles) {
-      const WaveSpan64<WSPAN> in(a.in, a.n, next * TILE + (int64_t)wave * WSPAN);
+      const Span in(a.in, a.n, span_base(next));
 #pragma unroll
       for (int c = KH; c < CH; ++c) {
         out.store(c, R[c]);

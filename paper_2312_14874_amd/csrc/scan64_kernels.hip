@@ -5,9 +5,11 @@
 namespace mi355scan {
 
 // 512 threads x 64 elements per tile (two per 16-byte group), one resident
-// workgroup per CU; [0 = integer, 1 = float64]
-const void *kScan64[2] = {(const void *)&scan64_tiles<OpsAddU64, 512, 64, 2>,
-                          (const void *)&scan64_tiles<OpsAddF64, 512, 64, 2>};
+// workgroup per CU; [0 = integer, 1 = float64][reverse]
+const void *kScan64[2][2] = {
+    {(const void *)&scan64_tiles<OpsAddU64, 512, 64, 2, false>, (const void *)&scan64_tiles<OpsAddU64, 512, 64, 2, true>},
+    {(const void *)&scan64_tiles<OpsAddF64, 512, 64, 2, false>, (const void *)&scan64_tiles<OpsAddF64, 512, 64, 2, true>},
+};
 const int kScan64Block = 512, kScan64Items = 64;
 
 }  // namespace mi355scan

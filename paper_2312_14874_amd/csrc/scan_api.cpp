@@ -355,7 +355,7 @@ scan_status_t flat64(const void *in, void *out, int64_t n, scan_dtype_t dt, uint
   int r = check_flags(flags);
   if (r == kOk) r = check_flat_sz(in, out, n, 8);
   if (r != kOk) return st(r);
-  if (flags & ~(uint32_t)SCAN_EXCLUSIVE) return SCAN_ERROR_NOT_SUPPORTED;   // forward +-scans only
+  if (flags & ~(uint32_t)(SCAN_EXCLUSIVE | SCAN_REVERSE)) return SCAN_ERROR_NOT_SUPPORTED;   // +-scans only
   if (((uintptr_t)in & 15u) || ((uintptr_t)out & 15u)) return SCAN_ERROR_INVALID_VALUE;
   if (n == 0) return SCAN_SUCCESS;
   ensure_init();
@@ -371,7 +371,7 @@ scan_status_t flat64(const void *in, void *out, int64_t n, scan_dtype_t dt, uint
     s = stream_ws(dev, stream, 2 * T, &ws);
     if (s != SCAN_SUCCESS) return s;
   }
-  const void *fn = kScan64[dt == SCAN_F64 ? 1 : 0];
+  const void *fn = kScan64[dt == SCAN_F64 ? 1 : 0][(flags & SCAN_REVERSE) ? 1 : 0];
   const int64_t grid = std::min<int64_t>(T, resident_grid(fn, kScan64Block, di.cus, 0, 100));
   KernelArgs a;
   std::memset(&a, 0, sizeof(a));

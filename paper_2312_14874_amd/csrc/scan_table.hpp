@@ -56,9 +56,9 @@ struct CompactKernels {
 extern const CompactKernels kCompact;
 extern const CompactKernels kPartition;   // two-way partition (set_count unused)
 
-// 64-bit scans (flat, forward, 16-byte aligned buffers): [0 = integer sum,
-// 1 = float64 sum].
-extern const void *kScan64[2];
+// 64-bit scans (flat, 16-byte aligned buffers): [0 = integer sum, 1 = float64
+// sum][reverse].
+extern const void *kScan64[2][2];
 extern const int kScan64Block, kScan64Items;
 
 }  // namespace mi355scan

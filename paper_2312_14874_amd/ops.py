@@ -16,7 +16,7 @@ from ._lib import (SCAN_EXCLUSIVE, SCAN_F32, SCAN_I32, SCAN_I64, SCAN_PRED_GREAT
 _DTYPES = {torch.int32: SCAN_I32, torch.float32: SCAN_F32}
 if hasattr(torch, "uint32"):
     _DTYPES[torch.uint32] = SCAN_U32
-# 64-bit elements: forward +-scans of cumsum only (the library refuses the rest)
+# 64-bit elements: +-scans of cumsum only (the library refuses the rest)
 _DTYPES[torch.int64] = SCAN_I64
 _DTYPES[torch.float64] = SCAN_F64
 if hasattr(torch, "uint64"):
@@ -73,7 +73,7 @@ def cumsum(x: torch.Tensor, exclusive: bool = False, reverse: bool = False, out=
 
     op: "sum" (any dtype), or "max" / "min" / "xor" for int32 (signed) and
     uint32.  out may be x itself (in place).  int64 / uint64 / float64
-    tensors take forward +-scans (exclusive or not; integers wrap modulo
+    tensors take +-scans (exclusive, reverse or not; integers wrap modulo
     2^64) and must start on a 16-byte boundary."""
     dt = _check_tensor(x, "x")
     out = _out_like(x, out)
@@ -191,9 +191,13 @@ def two_pass_cumsum(x: torch.Tensor, method: str = "accumulate_prefix", exclusiv
 
 
 def cumsum_backward(grad: torch.Tensor, offsets=None, out=None) -> torch.Tensor:
-    """Gradient of an inclusive float32 cumsum: per-segment suffix sums of grad."""
-    if _check_tensor(grad, "grad") != SCAN_F32:
-        raise TypeError("cumsum_backward takes float32")
+    """Gradient of an inclusive cumsum: per-segment suffix sums of grad
+    (float32; float64 without offsets)."""
+    dt = _check_tensor(grad, "grad")
+    if dt == SCAN_F64 and offsets is None:
+        return cumsum(grad, reverse=True, out=out)
+    if dt != SCAN_F32:
+        raise TypeError("cumsum_backward takes float32 (float64 without offsets)")
     out = _out_like(grad, out)
     with torch.cuda.device(grad.device):
         if offsets is None:
@@ -208,14 +212,15 @@ def cumsum_backward(grad: torch.Tensor, offsets=None, out=None) -> torch.Tensor:
 
 
 class CumsumFn(torch.autograd.Function):
-    """Differentiable float32 inclusive cumsum over a flat tensor or over the
-    ragged rows given by CSR offsets.  The backward is the reverse (suffix)
-    scan; nothing but the offsets is saved, because the map is linear."""
+    """Differentiable inclusive cumsum: float32 over a flat tensor or over the
+    ragged rows given by CSR offsets, float64 over a flat tensor.  The
+    backward is the reverse (suffix) scan; nothing but the offsets is saved,
+    because the map is linear."""
 
     @staticmethod
     def forward(ctx, x, offsets=None):
-        if x.dtype != torch.float32:
-            raise TypeError("CumsumFn takes float32")
+        if x.dtype != torch.float32 and not (x.dtype == torch.float64 and offsets is None):
+            raise TypeError("CumsumFn takes float32 (float64 without offsets)")
         xc = x.contiguous()
         y = cumsum(xc) if offsets is None else segmented_scan(xc, offsets)
         ctx.offsets = offsets

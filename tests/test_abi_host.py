@@ -141,11 +141,9 @@ def test_int64_argument_errors():
     assert f(4100, 8192, 10, U64, 0, None) == INVALID               # not 8-byte aligned
     assert f(4104, 8192, 10, I64, 0, None) == INVALID               # 8- but not 16-byte aligned
     assert f(4096, 4136, 10, I64, 0, None) == OVERLAP               # 8-byte elements overlap
-    assert f(4096, 8192, 10, I64, REV, None) == NOT_SUPPORTED       # forward only
     assert f(4096, 8192, 10, U64, OP_MAX, None) == NOT_SUPPORTED    # + only
     assert f(4096, 8192, 10, I64, 0x10, None) == INVALID            # unknown flag
     assert f(4104, 8192, 10, F64, 0, None) == INVALID               # float64: 16-byte alignment too
-    assert f(4096, 8192, 10, F64, REV | EXC, None) == NOT_SUPPORTED
     assert f(4096, 8192, 10, F64, OP_XOR, None) == NOT_SUPPORTED
     # the other entry points take 32-bit dtypes only
     assert L.lib.scan_segmented_batch(4096, 8192, 16, 1, 10, I64, 0, None) == NOT_SUPPORTED

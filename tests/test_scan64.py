@@ -1,7 +1,8 @@
-"""64-bit integer scans (scan_flat with SCAN_I64 / SCAN_U64) against the
-oracle, bit-exact: ragged sizes across tile boundaries, inclusive and
-exclusive, in place, carries out of the low 32 bits, wrap-around modulo 2^64,
-a workspace shared with 32-bit scans on one stream, and 2^28 elements."""
+"""64-bit scans (scan_flat with SCAN_I64 / SCAN_U64 / SCAN_F64) against the
+oracle: integers bit-exact, float64 within the summation bound; ragged sizes
+across tile boundaries, inclusive and exclusive, forward and reverse, in
+place, carries out of the low 32 bits, wrap-around modulo 2^64, a workspace
+shared with 32-bit scans on one stream, autograd, and 2^28 elements."""
 import numpy as np
 import pytest
 
@@ -22,11 +23,12 @@ def to_dev64(a: np.ndarray, pad: int = 2) -> torch.Tensor:
     return t[pad:]
 
 
-def run64(a: np.ndarray, exclusive=False, inplace=False) -> np.ndarray:
+def run64(a: np.ndarray, exclusive=False, inplace=False, reverse=False) -> np.ndarray:
     x = to_dev64(a)
     out = x if inplace else to_dev64(np.zeros(a.size, dtype=np.int64))
     dt = U64 if a.dtype == np.uint64 else I64
-    check_status(lib().scan_flat(x.data_ptr(), out.data_ptr(), a.size, dt, 1 if exclusive else 0, stream()),
+    flags = (1 if exclusive else 0) | (2 if reverse else 0)
+    check_status(lib().scan_flat(x.data_ptr(), out.data_ptr(), a.size, dt, flags, stream()),
                  "scan_flat n=%d" % a.size)
     torch.cuda.synchronize()
     return out.cpu().numpy().view(a.dtype)
@@ -43,18 +45,19 @@ def data(n, seed, dtype=np.uint64, kind="uniform"):
     return a.view(dtype)
 
 
-def check(a, exclusive=False, **kw):
-    want = oracle.scan_int64(a, exclusive=exclusive)
-    got = run64(a, exclusive, **kw)
+def check(a, exclusive=False, reverse=False, **kw):
+    want = oracle.scan_int64(a, exclusive=exclusive, reverse=reverse)
+    got = run64(a, exclusive, reverse=reverse, **kw)
     assert got.dtype == a.dtype
     err = first_mismatch(got.view(np.uint64), want.view(np.uint64))
-    assert not err, "n=%d ex=%d: %s" % (a.size, exclusive, err)
+    assert not err, "n=%d ex=%d rev=%d: %s" % (a.size, exclusive, reverse, err)
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 127, 128, 129, TILE - 1, TILE, TILE + 1, 5 * TILE + 777, (1 << 20) + 3])
 @pytest.mark.parametrize("exclusive", [False, True])
-def test_ragged(n, exclusive):
-    check(data(n, 6000 + n % 97), exclusive)
+@pytest.mark.parametrize("reverse", [False, True])
+def test_ragged(n, exclusive, reverse):
+    check(data(n, 6000 + n % 97), exclusive, reverse)
 
 
 @pytest.mark.parametrize("kind", ["uniform", "carry", "small"])
@@ -67,6 +70,7 @@ def test_value_patterns(kind, dtype):
 def test_in_place():
     check(data(11 * TILE + 5, 6200), inplace=True)
     check(data(11 * TILE + 5, 6201), exclusive=True, inplace=True)
+    check(data(11 * TILE + 5, 6202), reverse=True, inplace=True)
 
 
 def test_shares_workspace_with_32bit_scans():
@@ -93,12 +97,15 @@ def test_torch_binding():
     assert not first_mismatch(got, oracle.scan_int64(a))
     got = m.cumsum(x, exclusive=True).cpu().numpy()
     assert not first_mismatch(got, oracle.scan_int64(a, exclusive=True))
+    got = m.cumsum(x, reverse=True).cpu().numpy()
+    assert not first_mismatch(got, oracle.scan_int64(a, reverse=True))
     with pytest.raises(m.ScanError):
-        m.cumsum(x, reverse=True)
+        m.cumsum(x, op="max")
 
 
 def test_full_size():
     check(data(1 << 28, 6600), exclusive=False)
+    check(data(1 << 28, 6601), exclusive=True, reverse=True)
 
 
 # ---------------------------------------------------------------- float64
@@ -106,21 +113,22 @@ def test_full_size():
 F64 = 5
 
 
-def run_f64(a: np.ndarray, exclusive=False, inplace=False) -> np.ndarray:
+def run_f64(a: np.ndarray, exclusive=False, inplace=False, reverse=False) -> np.ndarray:
     x = torch.empty(a.size + 2, dtype=torch.float64, device="cuda")[2:]
     x.copy_(torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)))
     out = x if inplace else torch.zeros(a.size + 2, dtype=torch.float64, device="cuda")[2:]
-    check_status(lib().scan_flat(x.data_ptr(), out.data_ptr(), a.size, F64, 1 if exclusive else 0, stream()),
+    flags = (1 if exclusive else 0) | (2 if reverse else 0)
+    check_status(lib().scan_flat(x.data_ptr(), out.data_ptr(), a.size, F64, flags, stream()),
                  "scan_flat f64 n=%d" % a.size)
     torch.cuda.synchronize()
     return out.cpu().numpy()
 
 
-def check_f64(a, exclusive=False, **kw):
+def check_f64(a, exclusive=False, reverse=False, **kw):
     """Within the recursive-summation bound of the kernel's addition tree: at
     most 8 levels per tile of the look-back chain plus 128 inside a tile."""
-    ref, ab = oracle.scan_f64(a, exclusive=exclusive)
-    got = run_f64(a, exclusive, **kw)
+    ref, ab = oracle.scan_f64(a, exclusive=exclusive, reverse=reverse)
+    got = run_f64(a, exclusive, reverse=reverse, **kw)
     depth = 8 * (-(-a.size // TILE)) + 128
     tol = oracle.f64_tolerance(ab, depth)
     err = np.abs(got - ref)
@@ -135,8 +143,9 @@ def normal_f64(n, seed):
 
 @pytest.mark.parametrize("n", [1, 2, 3, 129, TILE - 1, TILE, TILE + 1, 5 * TILE + 777, (1 << 20) + 3])
 @pytest.mark.parametrize("exclusive", [False, True])
-def test_f64_ragged(n, exclusive):
-    check_f64(normal_f64(n, 6700 + n % 89), exclusive)
+@pytest.mark.parametrize("reverse", [False, True])
+def test_f64_ragged(n, exclusive, reverse):
+    check_f64(normal_f64(n, 6700 + n % 89), exclusive, reverse)
 
 
 def test_f64_values():
@@ -154,6 +163,23 @@ def test_f64_values():
 
 def test_f64_in_place():
     check_f64(normal_f64(9 * TILE + 3, 6900), inplace=True)
+    check_f64(normal_f64(9 * TILE + 3, 6901), reverse=True, inplace=True)
+
+
+def test_f64_autograd_gradcheck():
+    # the backward of the float64 cumsum is the reverse scan: torch's
+    # numerical Jacobian check, on a size that spans several tiles
+    import paper_2312_14874_amd as m
+    g = torch.Generator().manual_seed(7050)
+    x = torch.randn(2 * TILE + 17, generator=g, dtype=torch.float64).cuda().requires_grad_()
+    y = m.cumsum_autograd(x)
+    gy = torch.randn(x.numel(), generator=g, dtype=torch.float64).cuda()
+    (gx,) = torch.autograd.grad(y, x, gy)
+    ref, ab = oracle.scan_f64(gy.cpu().numpy(), reverse=True)
+    tol = oracle.f64_tolerance(ab, 8 * 3 + 128)
+    assert np.all(np.abs(gx.cpu().numpy() - ref) <= tol)
+    small = torch.randn(300, generator=g, dtype=torch.float64).cuda().requires_grad_()
+    assert torch.autograd.gradcheck(m.cumsum_autograd, (small,), eps=1e-6, atol=1e-8, rtol=1e-6)
 
 
 def test_f64_torch_binding():
@@ -167,3 +193,4 @@ def test_f64_torch_binding():
 
 def test_f64_full_size():
     check_f64(normal_f64(1 << 28, 7100))
+    check_f64(normal_f64(1 << 28, 7101), exclusive=True, reverse=True)
