@@ -194,3 +194,46 @@ def test_f64_torch_binding():
 def test_f64_full_size():
     check_f64(normal_f64(1 << 28, 7100))
     check_f64(normal_f64(1 << 28, 7101), exclusive=True, reverse=True)
+
+
+def test_capture_mixed_widths_after_reserve():
+    """A caller's graph holding a uint64 scan, a float64 reverse scan and a
+    32-bit scan on one stream's reserved workspace, replayed with eager calls
+    of the other widths on the same stream in between."""
+    import paper_2312_14874_amd as m
+    n = 3 * TILE * 5 + 77
+    g = np.random.default_rng(7200)
+    a64 = g.integers(0, 1 << 64, size=n, dtype=np.uint64)
+    f = g.standard_normal(n)
+    a32 = g.integers(-1 << 31, 1 << 31, size=4 * n, dtype=np.int64).astype(np.int32)
+    x64, xf, x32 = (torch.from_numpy(v).cuda() for v in (a64.view(np.int64), f, a32))
+    y64, yf, y32 = torch.empty_like(x64), torch.empty_like(xf), torch.empty_like(x32)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        m.reserve(4 * n)
+        m.cumsum(x64, out=y64)
+        m.cumsum(xf, reverse=True, out=yf)
+        m.cumsum(x32, out=y32)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        m.cumsum(x64, out=y64)
+        m.cumsum(xf, reverse=True, out=yf)
+        m.cumsum(x32, out=y32)
+    w64 = oracle.scan_int64(a64)
+    wf, ab = oracle.scan_f64(f, reverse=True)
+    w32 = oracle.scan_int(a32)
+    tol = oracle.f64_tolerance(ab, 8 * (-(-n // TILE)) + 128)
+    e64 = torch.empty_like(x64)
+    for rep in range(4):
+        for t in (y64, yf, y32):
+            t.zero_()
+        with torch.cuda.stream(s):
+            graph.replay()
+            m.cumsum(x32, exclusive=True, out=torch.empty_like(x32))   # eager, same workspace
+            m.cumsum(x64, exclusive=True, out=e64)
+        torch.cuda.synchronize()
+        assert not first_mismatch(y64.cpu().numpy().view(np.uint64), w64), rep
+        assert np.all(np.abs(yf.cpu().numpy() - wf) <= tol), rep
+        assert not first_mismatch(y32.cpu().numpy(), w32), rep
+        assert not first_mismatch(e64.cpu().numpy().view(np.uint64), oracle.scan_int64(a64, exclusive=True)), rep
