@@ -98,3 +98,10 @@ def test_torch_binding():
 def test_full_size():
     a = data(1 << 28, 7900, np.int32, zero_frac=0.5)
     check(a, "greater", 0)
+
+
+def test_beyond_2p30_elements():
+    # byte offsets past 2^32: the output ranges are addressed from per-wave bases
+    n = (1 << 30) + 7
+    a = data(n, 8000, np.uint32, zero_frac=0.3)
+    check(a, "nonzero")

@@ -237,3 +237,8 @@ def test_capture_mixed_widths_after_reserve():
         assert np.all(np.abs(yf.cpu().numpy() - wf) <= tol), rep
         assert not first_mismatch(y32.cpu().numpy(), w32), rep
         assert not first_mismatch(e64.cpu().numpy().view(np.uint64), oracle.scan_int64(a64, exclusive=True)), rep
+
+
+def test_beyond_2p32_bytes():
+    # 2^29 + 3 uint64 elements: 4 GiB per buffer, byte offsets past 2^32
+    check(data((1 << 29) + 3, 8100), exclusive=False)
