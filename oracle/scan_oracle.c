@@ -137,7 +137,9 @@ void oracle_scan_u64(const uint64_t *a, uint64_t *out, int64_t n, int exclusive,
  * returns the rounded sum and its exact rounding error; the error joins lo
  * and the pair is renormalised (Dekker's Fast2Sum), so hi is the total
  * rounded to float64 and the accumulated error stays near n * 2^-106 *
- * sum|a|, far below one float64 rounding.  abs_out[i] (may be NULL): the
+ * sum|a|, far below one float64 rounding.  Non-finite inputs: once the
+ * running total is infinite or NaN it is the plain IEEE sum (a NaN stays, an
+ * infinity keeps its sign until the opposite one makes it NaN).  abs_out[i] (may be NULL): the
  * plain float64 running sum of |a|, the scale of the tolerance.  Reverse
  * runs the pass from the last element down (suffix sums). */
 static void two_sum(double a, double b, double *s, double *e)
@@ -163,9 +165,17 @@ void oracle_scan_f64(const double *a, double *out, double *abs_out, int64_t n, i
         }
         double s, e;
         two_sum(hi, x, &s, &e);
-        e += lo;
-        hi = s + e;               /* Fast2Sum: |s| >= |e| after TwoSum */
-        lo = e - (hi - s);
+        if (!isfinite(s)) {
+            /* an infinite or NaN total has no rounding error to carry (and
+             * TwoSum's inf - inf would turn +inf into NaN): the plain IEEE
+             * sum, so NaN and infinities behave as in the definition */
+            hi = s;
+            lo = 0.0;
+        } else {
+            e += lo;
+            hi = s + e;           /* Fast2Sum: |s| >= |e| after TwoSum */
+            lo = e - (hi - s);
+        }
         aacc += fabs(x);
         if (!exclusive) {
             out[i] = hi;

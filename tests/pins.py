@@ -441,6 +441,133 @@ def pin_f32_segmented(seg_f32) -> list:
     return fails
 
 
+# ---------------------------------------------------------------- non-finite values
+# Reading of the definition for IEEE inputs: every output is a sum of its
+# prefix (suffix for reverse scans), so its class follows from the terms it
+# contains -- NaN if one of them is NaN or both infinities occur, +inf / -inf
+# if only that infinity occurs, finite otherwise (finite overflow aside).
+# These classes are worked out here term by term in plain Python, apart from
+# the oracle's arithmetic; zeros of either sign compare equal.
+
+def _same_float(got, want) -> bool:
+    g = np.asarray(got, dtype=np.float64)
+    w = np.asarray(want, dtype=np.float64)
+    if g.shape != w.shape:
+        return False
+    return bool(np.all(np.where(np.isnan(w), np.isnan(g), g == w)))
+
+
+FINITE, POS_INF, NEG_INF, NAN = 0, 1, 2, 3
+
+
+def _prefix_classes(v) -> np.ndarray:
+    """Class of each inclusive prefix sum of v, term by term."""
+    out = np.empty(len(v), dtype=np.int8)
+    pos = neg = nan = False
+    for i, x in enumerate(v):
+        x = float(x)
+        if x != x:
+            nan = True
+        elif x == math.inf:
+            pos = True
+        elif x == -math.inf:
+            neg = True
+        out[i] = NAN if nan or (pos and neg) else (POS_INF if pos else (NEG_INF if neg else FINITE))
+    return out
+
+
+def _scan_classes(v, exclusive, reverse) -> np.ndarray:
+    w = v[::-1] if reverse else v
+    c = _prefix_classes(w)
+    if exclusive and c.size:
+        c = np.concatenate([[FINITE], c[:-1]]).astype(np.int8)
+    return c[::-1] if reverse else c
+
+
+def _class_of(s) -> np.ndarray:
+    s = np.asarray(s, dtype=np.float64)
+    return np.where(np.isnan(s), NAN, np.where(s == np.inf, POS_INF,
+                    np.where(s == -np.inf, NEG_INF, FINITE))).astype(np.int8)
+
+
+def _inject_nonfinite(rng, v):
+    """v with 0-3 NaN / +inf / -inf planted at random positions."""
+    kinds = rng.choice([np.nan, np.inf, -np.inf], size=int(rng.integers(0, 4)))
+    v = v.copy()
+    v[rng.integers(0, v.size, size=kinds.size)] = kinds
+    return v
+
+
+def pin_nonfinite(scan_f, dtype) -> list:
+    """scan_f(a, exclusive, reverse) -> (sums float64, abs_sums float64) for
+    float input of `dtype` (float32 or float64)."""
+    fails = []
+    g = golden_io.load("nonfinite.txt", conv=float)
+    modes = (("inclusive", False, False), ("exclusive", True, False),
+             ("reverse_inclusive", False, True), ("reverse_exclusive", True, True))
+    for case in ("inf", "nan", "zero", "mix"):
+        a = np.array(g[case + "_input"], dtype=dtype)
+        for key, ex, rev in modes:
+            if case + "_" + key in g and not _same_float(scan_f(a, ex, rev)[0], g[case + "_" + key]):
+                fails.append("golden %s_%s" % (case, key))
+        for key, ex in (("abs_inclusive", False), ("abs_exclusive", True)):
+            if case + "_" + key in g and not _same_float(scan_f(a, ex, False)[1], g[case + "_" + key]):
+                fails.append("golden %s_%s" % (case, key))
+
+    # classes term by term on random inputs with planted NaN / infinities;
+    # where every term is finite the value is the sequential sum of those
+    # terms (bit-equal for float32 input summed in float64, within the
+    # recursive-summation bound for the float64 reference)
+    rng = np.random.default_rng(23)
+    for trial in range(24):
+        n = int(rng.integers(1, 3000))
+        v = _inject_nonfinite(rng, rng.standard_normal(n).astype(dtype))
+        for ex in (False, True):
+            for rev in (False, True):
+                s, ab = scan_f(v, ex, rev)
+                if not np.array_equal(_class_of(s), _scan_classes(v, ex, rev)):
+                    fails.append("classes trial %d ex=%d rev=%d" % (trial, ex, rev))
+                if not np.array_equal(_class_of(ab), _scan_classes(np.abs(v), ex, rev)):
+                    fails.append("abs classes trial %d ex=%d rev=%d" % (trial, ex, rev))
+                w = (v[::-1] if rev else v).astype(np.float64)
+                with np.errstate(invalid="ignore"):
+                    part = np.add.accumulate(w)
+                fin = np.isfinite(part)            # prefixes of finite terms only
+                seq = np.where(fin, part, 0.0)
+                scale = np.add.accumulate(np.where(fin, np.abs(w), 0.0))
+                if ex:
+                    seq, scale = np.concatenate([[0.0], seq[:-1]]), np.concatenate([[0.0], scale[:-1]])
+                    fin = np.concatenate([[True], fin[:-1]])
+                if rev:
+                    seq, scale, fin = seq[::-1], scale[::-1], fin[::-1]
+                tol = 0.0 if dtype == np.float32 else (n + 1) * 2.0**-53 * scale
+                with np.errstate(invalid="ignore"):
+                    bad = fin & ~(np.abs(np.asarray(s, dtype=np.float64) - seq) <= tol)
+                if np.any(bad):
+                    fails.append("finite values trial %d ex=%d rev=%d" % (trial, ex, rev))
+    return fails
+
+
+def pin_nonfinite_segmented(seg_f) -> list:
+    """seg_f(a, offsets, exclusive, reverse) -> (sums, abs_sums) for float32
+    input: the classes restart with every segment."""
+    fails = []
+    rng = np.random.default_rng(29)
+    for trial in range(12):
+        n = int(rng.integers(1, 4000))
+        v = _inject_nonfinite(rng, rng.standard_normal(n).astype(np.float32))
+        cuts = np.sort(rng.integers(0, n + 1, size=int(rng.integers(0, 30))))
+        off = np.concatenate([[0], cuts, [n]]).astype(np.int64)
+        for ex in (False, True):
+            for rev in (False, True):
+                want = np.concatenate([_scan_classes(v[off[s]:off[s + 1]], ex, rev)
+                                       for s in range(off.size - 1)])
+                s, _ = seg_f(v, off, ex, rev)
+                if not np.array_equal(_class_of(s), want):
+                    fails.append("segmented classes trial %d ex=%d rev=%d" % (trial, ex, rev))
+    return fails
+
+
 # ---------------------------------------------------------------- other operators
 
 _IDENT = {("max", True): -(1 << 31), ("max", False): 0,

@@ -350,3 +350,91 @@ def _mp_off_by_one(a, pred, thr):
 @pytest.mark.parametrize("mutant", [_mp_rejected_in_order, _mp_swapped, _mp_off_by_one])
 def test_pins_catch_partition_mutant(mutant):
     assert pins.pin_partition(mutant) != []
+
+
+# ---------------------------------------------------------------- non-finite values
+
+def _f64(a, ex, rev):
+    return oracle.scan_f64(a, exclusive=ex, reverse=rev)
+
+
+def test_oracle_f32_nonfinite_pinned():
+    assert pins.pin_nonfinite(_f, np.float32) == []
+
+
+def test_oracle_f32_segmented_nonfinite_pinned():
+    assert pins.pin_nonfinite_segmented(_segf) == []
+
+
+def test_oracle_f64_nonfinite_pinned():
+    assert pins.pin_nonfinite(_f64, np.float64) == []
+
+
+def _mnf_abs_skips_nan(a, ex, rev):
+    # a tolerance scale that stays finite after a NaN
+    s, _ = oracle.scan_f32(a, exclusive=ex, reverse=rev)
+    v = np.abs(np.asarray(a, dtype=np.float64))
+    v = v[::-1] if rev else v
+    ab = np.nancumsum(v) - (np.nan_to_num(v, nan=0.0) if ex else 0)
+    return s, (ab[::-1] if rev else ab)
+
+
+def _mnf_sum_drops_nan(a, ex, rev):
+    # NaN read as 0 in the running total
+    a = np.asarray(a, dtype=np.float32)
+    _, ab = oracle.scan_f32(a, exclusive=ex, reverse=rev)
+    s, _ = oracle.scan_f32(np.where(np.isnan(a), np.float32(0), a), exclusive=ex, reverse=rev)
+    return s, ab
+
+
+def _mnf_inf_minus_inf_zero(a, ex, rev):
+    # +inf + -inf taken as 0 instead of NaN
+    s, ab = oracle.scan_f32(a, exclusive=ex, reverse=rev)
+    a = np.asarray(a, dtype=np.float32)
+    nan_in = np.isnan(a).any()
+    if not nan_in:
+        s = np.where(np.isnan(s), 0.0, s)
+    return s, ab
+
+
+def _mf64_unguarded_two_sum(a, ex, rev):
+    # double-double accumulation whose TwoSum error term is used even when the
+    # sum is infinite (inf - inf = NaN turns +inf into NaN)
+    v = np.asarray(a, dtype=np.float64)
+    idx = range(v.size - 1, -1, -1) if rev else range(v.size)
+    s = np.empty(v.size)
+    ab = np.empty(v.size)
+    hi = lo = aacc = 0.0
+    with np.errstate(invalid="ignore", over="ignore"):
+        for i in idx:
+            x = float(v[i])
+            if ex:
+                s[i], ab[i] = hi, aacc
+            t = hi + x
+            bv = t - hi
+            e = ((hi - (t - bv)) + (x - bv)) + lo
+            hi, lo = t + e, e - ((t + e) - t)
+            aacc += abs(x)
+            if not ex:
+                s[i], ab[i] = hi, aacc
+    return s, ab
+
+
+@pytest.mark.parametrize("mutant", [_mnf_abs_skips_nan, _mnf_sum_drops_nan, _mnf_inf_minus_inf_zero])
+def test_nonfinite_pins_catch_f32_mutant(mutant):
+    assert pins.pin_nonfinite(mutant, np.float32) != []
+
+
+def test_nonfinite_pins_catch_f64_mutant():
+    assert pins.pin_nonfinite(_mf64_unguarded_two_sum, np.float64) != []
+
+
+def _mnf_seg_nan_leaks(a, off, ex, rev):
+    # the segment restart clears the value but not a sticky NaN state
+    s, ab = oracle.segmented_f32(a, off, exclusive=ex, reverse=rev)
+    flat, _ = oracle.scan_f32(a, exclusive=ex, reverse=rev)
+    return np.where(np.isnan(flat), np.nan, s), ab
+
+
+def test_nonfinite_pins_catch_segmented_mutant():
+    assert pins.pin_nonfinite_segmented(_mnf_seg_nan_leaks) != []
