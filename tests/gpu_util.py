@@ -82,13 +82,31 @@ def configs():
     return [m.config_info(c) for c in range(m.num_configs())]
 
 
+def f32_bad(got: np.ndarray, ref: np.ndarray, abs_sums: np.ndarray, exp: int = -20) -> np.ndarray:
+    """Indices where a float result fails the acceptance rule against the
+    float64 oracle: where ref is finite, got must be finite and within
+    2^exp * running sum of |a| of it (a NaN or infinite output fails: the
+    test is written so that a NaN compares as out of bound); where ref is
+    NaN, got must be NaN; where ref is +-inf, got must be the same infinity.
+    -0.0 and +0.0 compare equal."""
+    g = np.asarray(got).astype(np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    fin = np.isfinite(ref)
+    tol = np.ldexp(np.asarray(abs_sums, dtype=np.float64), exp)
+    with np.errstate(invalid="ignore"):
+        ok_fin = np.abs(g - ref) <= tol
+        ok_nf = np.where(np.isnan(ref), np.isnan(g), g == ref)
+    return np.nonzero(np.where(fin, ~ok_fin, ~ok_nf))[0]
+
+
 def assert_f32_close(got: np.ndarray, ref: np.ndarray, abs_sums: np.ndarray, what=""):
-    """float32 acceptance: |got - ref| <= 2^-20 * running sum of |a| (ref: float64 oracle)."""
-    tol = np.ldexp(abs_sums, -20)
-    err = np.abs(got.astype(np.float64) - ref)
-    bad = np.nonzero(err > tol)[0]
-    assert bad.size == 0, "%s: %d elements out of bound, first %d: got %r ref %r tol %r" % (
-        what, bad.size, bad[0], float(got[bad[0]]), float(ref[bad[0]]), float(tol[bad[0]]))
+    """float32 acceptance: |got - ref| <= 2^-20 * running sum of |a| (ref: float64
+    oracle), non-finite values matched by class (see f32_bad)."""
+    bad = f32_bad(got, ref, abs_sums)
+    if bad.size:
+        i = int(bad[0])
+        raise AssertionError("%s: %d elements out of bound, first %d: got %r ref %r tol %r" % (
+            what, bad.size, i, float(got[i]), float(ref[i]), float(np.ldexp(abs_sums[i], -20))))
 
 
 def first_mismatch(got: np.ndarray, want: np.ndarray) -> str:
