@@ -52,9 +52,12 @@ def test_f32_every_config(cfg):
                     assert got[first] == 0.0
 
 
-@pytest.mark.parametrize("cfg", [0, 4, 6, 9])
+@pytest.mark.parametrize("cfg", range(NUM_CONFIGS))
 def test_f32_exact_when_sums_representable(cfg):
-    # integers in [-2, 2], n <= 2^22: every partial sum fits in 24 bits
+    # integers in [-2, 2], n <= 2^22: every partial sum fits in 24 bits, so
+    # every association gives the same bits and a dropped or repeated
+    # element anywhere shows (the 2^-20 bound alone would miss one near the
+    # end of a long array)
     for n in (5000, 1 << 20, (1 << 22) - 3):
         a = workloads.small_int_f32(n, seed=n)
         for ex in (False, True):

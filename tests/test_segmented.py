@@ -45,6 +45,22 @@ def test_f32_segments(cfg):
             assert_f32_close(got, ref, ab, "cfg %d ex %d rev %d" % (cfg, ex, rev))
 
 
+@pytest.mark.parametrize("cfg", range(NUM_CONFIGS))
+def test_f32_segments_exact_when_sums_representable(cfg):
+    # integer-valued float32 in [-2, 2], n < 2^22: every partial sum is exact,
+    # so the segmented float32 kernels must match the oracle bit for bit
+    g = np.random.default_rng(900 + cfg)
+    n = (1 << 22) - 5
+    a = workloads.small_int_f32(n, seed=cfg)
+    off = workloads.random_offsets(g, n, 500)
+    for ex in (False, True):
+        for rev in (False, True):
+            got = segmented(a, off, exclusive=ex, reverse=rev, cfg=cfg)
+            ref, _ = oracle.segmented_f32(a, off, exclusive=ex, reverse=rev, with_abs=False)
+            assert np.array_equal(got.astype(np.float64), ref), "cfg %d ex %d rev %d: %s" % (
+                cfg, ex, rev, first_mismatch(got.astype(np.float64), ref))
+
+
 def test_special_segmentations():
     n = 100_003
     a = workloads.full_u32(n, seed=3)
