@@ -37,6 +37,15 @@
  *  - No function aborts or throws across the ABI; a failing HIP call is
  *    reported as SCAN_ERROR_LAUNCH / SCAN_ERROR_OUT_OF_MEMORY and its hipError_t
  *    is kept for scan_last_hip_error().
+ *  - Device-side waits (a tile waiting for its predecessors' status words)
+ *    are bounded (scan_set_spin_limit).  A wait that gives up lets the kernel
+ *    finish and raises the error word of the stream (or library graph) it ran
+ *    on; that call's results are invalid.  The word lives in host memory and
+ *    is read without synchronising: the next call on the same stream (the
+ *    next scan_graph_launch of the same graph) that finds it raised returns
+ *    SCAN_ERROR_TIMEOUT, clears it and enqueues nothing.  A call made while
+ *    the failing kernel is still running cannot see it yet; the first one
+ *    after it has finished does (scan_check_device_error waits for that).
  *  - Integer scans wrap modulo 2^32 (2^64 for 64-bit elements); signed and
  *    unsigned types of one width give identical bits.
  *  - float32 scans: the result is within 2^-20 * sum_{j<=i} |a_j| of the exact
@@ -201,12 +210,19 @@ scan_status_t scan_f32_backward(const float *grad_out, float *grad_in, int64_t n
 /* ---- workspace ----
  * Each stream owns a workspace (tile status words and counters) that is
  * allocated on first use and grown when a larger n arrives; growing
- * synchronises the stream and is refused during stream capture.  Call
- * scan_reserve(max_n) before capturing library calls into a graph.
+ * synchronises the stream and is refused during stream capture (returns
+ * SCAN_ERROR_CAPTURE).  Call scan_reserve(max_n) before capturing library
+ * calls into a graph of your own.  Growing never frees the allocation it
+ * replaces: a graph captured from calls on this stream keeps using it and
+ * stays valid (and exact) after later, larger eager calls.  Replays of such
+ * graphs, and eager calls on the stream, must not overlap in time.
  * The workspace keeps itself clean between launches (no reset kernel or
  * memset is needed per call). */
 scan_status_t scan_reserve(int64_t max_n, hipStream_t stream);
-scan_status_t scan_release(hipStream_t stream);   /* synchronises the stream */
+/* Frees every workspace the stream has used (current and outgrown) and its
+ * error word; synchronises the stream.  Graphs captured from this stream's
+ * calls become invalid: destroy them first. */
+scan_status_t scan_release(hipStream_t stream);
 
 /* ---- graphs ----
  * Capture a batched segmented scan (both kernels) into a hipGraph with its own
@@ -221,7 +237,13 @@ scan_status_t scan_segmented_graph_create(const void *in, void *out, const int64
 scan_status_t scan_looped_graph_create(const void *in, void *out, const int64_t *host_offsets,
                                        int32_t num_segments, scan_dtype_t dtype,
                                        uint32_t flags, hipStream_t stream, void **graph);
+/* Replays a graph; returns SCAN_ERROR_TIMEOUT (and replays nothing) when an
+ * earlier replay of this graph gave up a device-side wait. */
 scan_status_t scan_graph_launch(void *graph, hipStream_t stream);
+/* Reads and clears the graph's error word without synchronising: call it
+ * after the replay has finished (e.g. after synchronising its stream).
+ * SCAN_SUCCESS or SCAN_ERROR_TIMEOUT. */
+scan_status_t scan_graph_check_device_error(void *graph);
 scan_status_t scan_graph_destroy(void *graph);
 
 /* Comparator: one flat-scan launch per segment, enqueued eagerly from the
@@ -271,12 +293,14 @@ scan_status_t scan_tune_load(const char *path);
 /* ---- diagnostics ---- */
 const char   *scan_status_string(scan_status_t status);
 int32_t       scan_last_hip_error(void);
-/* Spin limit for device-side waits (iterations; 0 restores the default).  A
- * wait that exceeds it gives up, marks the workspace's error word and lets the
- * kernel finish (the results of that call are then invalid). */
+/* Spin limit for device-side waits (sleeping polls; 0 restores the default
+ * of 2^16, about 0.1 s).  A wait that exceeds it gives up, raises the error
+ * word of the stream or graph and lets the kernel finish (the results of that
+ * call are then invalid).  Applies to launches enqueued (or graphs created)
+ * after the call. */
 scan_status_t scan_set_spin_limit(uint32_t limit);
-/* Synchronise `stream`, read and clear the device error word of its
- * workspace: SCAN_SUCCESS or SCAN_ERROR_TIMEOUT. */
+/* Synchronise `stream`, read and clear its error word: SCAN_SUCCESS or
+ * SCAN_ERROR_TIMEOUT. */
 scan_status_t scan_check_device_error(hipStream_t stream);
 
 #ifdef __cplusplus

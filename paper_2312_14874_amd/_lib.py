@@ -52,6 +52,7 @@ SIGNATURES = {
     "scan_segmented_graph_create": (ST, [P, P, P, I32, I64, ST, U32, P, ctypes.POINTER(P)]),
     "scan_looped_graph_create": (ST, [P, P, P, I32, ST, U32, P, ctypes.POINTER(P)]),
     "scan_graph_launch": (ST, [P, P]),
+    "scan_graph_check_device_error": (ST, [P]),
     "scan_graph_destroy": (ST, [P]),
     "scan_segmented_looped": (ST, [P, P, P, I32, ST, U32, P]),
     "scan_num_configs": (I32, []),
@@ -76,6 +77,9 @@ class ScanError(RuntimeError):
         msg = "%s failed: %s (%d)" % (what or "scan call", self.name, status)
         if status == 4:
             msg += ", hipError_t %d" % _lib.scan_last_hip_error()
+        if status == 7:
+            msg += (": a device-side wait of an earlier call on this stream (or graph) gave up, so that"
+                    " call's results are invalid; this call enqueued nothing")
         super().__init__(msg)
 
 

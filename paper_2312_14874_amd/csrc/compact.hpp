@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
       if (t > 0) {
         uint64_t w[K];
         lb_window<Op, K>(st, (int32_t)t - 1, w);
-        carry = look_back<Op, K>(st, t, ka.spin_limit, ka.hdr, w);
+        carry = look_back<Op, K>(st, t, ka.spin_limit, ka.err, w);
         if (lane == 0) st_agent(st + t, Op::pack(carry + agg, kPrefix));
       }
       if (lane == 0) s_carry = carry;
@@ -115,9 +115,13 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
     // kept elements go to out[carry + wpre + (kept in the wave's earlier
     // chunks) + (kept in earlier lanes of the chunk) + (kept before k in the group)]
     const uint32_t base = carry + wpre;
+    // the kept elements' range out[base, n), clamped to [0, 2^31) bytes: a
+    // start beyond n (only after a look-back that gave up) writes nothing
+    const int64_t kbytes = (ka.n - (int64_t)base) * 4;
+    const bool kok = kbytes > 0;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        static_cast<uint32_t *>(ka.out) + base, (short)0,
-        (int)((ka.n - (int64_t)base) * 4 > 0x7fffffff ? 0x7fffffff : (ka.n - (int64_t)base) * 4), 0x00020000);
+        static_cast<uint32_t *>(ka.out) + (kok ? base : 0u), (short)0,
+        kok ? (int)(kbytes > 0x7fffffff ? 0x7fffffff : kbytes) : 0, 0x00020000);
     uint32_t *stage = s_stage[wave];
     uint32_t cb = 0u;   // kept in the wave's chunks so far (uniform)
     // partition: the wave's rejected elements go to out[rlo, rlo + rej) in

@@ -117,7 +117,7 @@ __device__ __forceinline__ int64_t acquire_tile64(const KernelArgs &a, uint32_t 
 // Carry into tile t (one wave): sum of the aggregates back to the nearest
 // PREFIX, read 64 tiles per poll (lane l: tile t-1-l of the window).
 template <class Op>
-__device__ uint64_t look_back64(const uint64_t *st, int64_t t, uint32_t spin_limit, WsHeader *hdr) {
+__device__ uint64_t look_back64(const uint64_t *st, int64_t t, uint32_t spin_limit, uint32_t *err) {
   const int lane = (int)(opaque_tid() & 63u);
   uint64_t acc = 0;
   int64_t base = t - 1;
@@ -135,7 +135,7 @@ __device__ uint64_t look_back64(const uint64_t *st, int64_t t, uint32_t spin_lim
     const int dP = bP ? __builtin_ctzll(bP) : 64, dE = bE ? __builtin_ctzll(bE) : 64;
     if (dE < dP) {
       if (++spins > spin_limit) {
-        if (lane == 0) st_agent32(&hdr->error, 1u);
+        if (lane == 0) raise_error(err);
         return acc;
       }
       __builtin_amdgcn_s_sleep(1);
@@ -261,7 +261,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan64_tiles(KernelArgs a) {
         if (lane == 0) publish64(st, t, agg, kPrefix);
       } else {
         if (lane == 0) publish64(st, t, agg, kAgg);
-        carry = look_back64<Op>(st, t, a.spin_limit, a.hdr);
+        carry = look_back64<Op>(st, t, a.spin_limit, a.err);
         if (lane == 0) publish64(st, t, Op::add(carry, agg), kPrefix);
       }
       if (lane == 0) s_carry = carry;

@@ -88,8 +88,38 @@ struct Workspace {
   uint64_t *status = nullptr;
   uint32_t *map = nullptr;
   uint64_t *sums = nullptr;   // two-pass scans: capacity tile totals + one running total
+  uint32_t *err = nullptr;    // error word the kernels raise on a timeout (device view)
   int64_t capacity = 0;   // tiles
 };
+
+// A word of pinned, coherent host memory that kernels raise (system-scope
+// store) when a wait gives up: the host reads it without synchronising.
+scan_status_t err_alloc(uint32_t **host, uint32_t **dev) {
+  void *p = nullptr;
+  hipError_t e = hipHostMalloc(&p, 64, hipHostMallocMapped | hipHostMallocCoherent);
+  if (e != hipSuccess) return hip_fail(e, SCAN_ERROR_OUT_OF_MEMORY);
+  void *d = nullptr;
+  e = hipHostGetDevicePointer(&d, p, 0);
+  if (e != hipSuccess) {
+    (void)hipHostFree(p);
+    return hip_fail(e);
+  }
+  __atomic_store_n(static_cast<uint32_t *>(p), 0u, __ATOMIC_RELEASE);
+  *host = static_cast<uint32_t *>(p);
+  *dev = static_cast<uint32_t *>(d);
+  return SCAN_SUCCESS;
+}
+
+void err_free(uint32_t **host, uint32_t **dev) {
+  if (*host) (void)hipHostFree(*host);
+  *host = nullptr;
+  *dev = nullptr;
+}
+
+// Read and clear an error word: true if a wait gave up since the last read.
+bool take_error(uint32_t *host) {
+  return host && __atomic_exchange_n(host, 0u, __ATOMIC_ACQ_REL) != 0u;
+}
 
 constexpr size_t kStatusOffset = sizeof(WsHeader) + kPubWords * sizeof(uint64_t);
 
@@ -126,7 +156,29 @@ void ws_free(Workspace *w) {
   *w = Workspace();
 }
 
-std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+// Per (device, stream): the current workspace, the allocations it outgrew
+// (kept until scan_release: graphs captured from this stream's calls still
+// use them) and the stream's error word, shared by all of them.
+struct StreamState {
+  Workspace ws;
+  std::vector<Workspace> retired;
+  uint32_t *err_host = nullptr;
+  uint32_t *err_dev = nullptr;
+};
+std::map<std::pair<int, hipStream_t>, StreamState> g_ws;
+
+// A timeout raised by an earlier launch on this stream is reported (once) by
+// the next call, which then enqueues nothing: its results could not be told
+// apart from those of the call that failed.
+scan_status_t stream_pending(int device, hipStream_t stream) {
+  uint32_t *h = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_ws.find(std::make_pair(device, stream));
+    if (it != g_ws.end()) h = it->second.err_host;
+  }
+  return take_error(h) ? SCAN_ERROR_TIMEOUT : SCAN_SUCCESS;
+}
 
 int64_t min_tile() {
   int64_t m = (int64_t)kUnalignedShape.block * kUnalignedShape.items;
@@ -136,26 +188,33 @@ int64_t min_tile() {
 
 int64_t tiles_for(int64_t n, int64_t tile) { return (n + tile - 1) / tile; }
 
+// The stream's workspace with room for `need` tiles.  Growing allocates a
+// new one and retires the old one without freeing it: a graph the caller
+// captured from this stream's calls keeps using the old allocation, which
+// stays valid and clean until scan_release.
 scan_status_t stream_ws(int device, hipStream_t stream, int64_t need, Workspace **out) {
   std::lock_guard<std::mutex> lk(g_mu);
-  Workspace &w = g_ws[std::make_pair(device, stream)];
-  if (w.base && w.capacity >= need) {
-    *out = &w;
+  StreamState &ss = g_ws[std::make_pair(device, stream)];
+  if (ss.ws.base && ss.ws.capacity >= need) {
+    *out = &ss.ws;
     return SCAN_SUCCESS;
   }
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   hipError_t e = hipStreamIsCapturing(stream, &cs);
   if (e != hipSuccess) return hip_fail(e);
   if (cs != hipStreamCaptureStatusNone) return SCAN_ERROR_CAPTURE;
-  const int64_t cap = std::max<int64_t>({need, 2 * w.capacity, 1024});
-  if (w.base) {
-    e = hipStreamSynchronize(stream);   // the old workspace may still be in use
-    if (e != hipSuccess) return hip_fail(e);
-    ws_free(&w);
+  if (!ss.err_host) {
+    scan_status_t s = err_alloc(&ss.err_host, &ss.err_dev);
+    if (s != SCAN_SUCCESS) return s;
   }
-  scan_status_t s = ws_alloc(&w, device, cap, stream);
+  const int64_t cap = std::max<int64_t>({need, 2 * ss.ws.capacity, 1024});
+  Workspace nw;
+  scan_status_t s = ws_alloc(&nw, device, cap, stream);
   if (s != SCAN_SUCCESS) return s;
-  *out = &w;
+  nw.err = ss.err_dev;
+  if (ss.ws.base) ss.retired.push_back(ss.ws);
+  ss.ws = nw;
+  *out = &ss.ws;
   return SCAN_SUCCESS;
 }
 
@@ -261,6 +320,10 @@ scan_status_t launch(const Call &c, hipStream_t stream, Workspace *ws_override, 
   DeviceInfo di;
   scan_status_t s = current_device(&dev, &di);
   if (s != SCAN_SUCCESS) return s;
+  if (!ws_override) {
+    s = stream_pending(dev, stream);
+    if (s != SCAN_SUCCESS) return s;
+  }
   const int cfg = cfg_override >= 0 ? cfg_override : select_config(c.opclass, c.seg, c.n);
   const KernelShape &sh = call_shape(c, cfg);
   const int mode = call_mode(c, cfg);
@@ -298,6 +361,7 @@ scan_status_t launch(const Call &c, hipStream_t stream, Workspace *ws_override, 
     std::lock_guard<std::mutex> lk(g_mu);
     a.spin_limit = g_spin_limit;
   }
+  a.err = ws ? ws->err : nullptr;
   a.exclusive = (c.flags & SCAN_EXCLUSIVE) ? 1u : 0u;
   a.reverse = (c.flags & SCAN_REVERSE) ? 1u : 0u;
   a.key = c.key;
@@ -363,6 +427,8 @@ scan_status_t flat64(const void *in, void *out, int64_t n, scan_dtype_t dt, uint
   DeviceInfo di;
   scan_status_t s = current_device(&dev, &di);
   if (s != SCAN_SUCCESS) return s;
+  s = stream_pending(dev, stream);
+  if (s != SCAN_SUCCESS) return s;
   const int64_t tile = (int64_t)kScan64Block * kScan64Items;
   const int64_t T = tiles_for(n, tile);
   if (2 * T > kMaxTiles) return SCAN_ERROR_NOT_SUPPORTED;
@@ -387,6 +453,7 @@ scan_status_t flat64(const void *in, void *out, int64_t n, scan_dtype_t dt, uint
     std::lock_guard<std::mutex> lk(g_mu);
     a.spin_limit = g_spin_limit;
   }
+  a.err = ws ? ws->err : nullptr;
   a.exclusive = (flags & SCAN_EXCLUSIVE) ? 1u : 0u;
   void *args[] = {&a};
   hipError_t e = hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kScan64Block), args, 0, stream);
@@ -440,6 +507,8 @@ scan_status_t two_pass(const void *in, void *out, int64_t n, scan_dtype_t dt, ui
   int dev = 0;
   DeviceInfo di;
   scan_status_t s = current_device(&dev, &di);
+  if (s != SCAN_SUCCESS) return s;
+  s = stream_pending(dev, stream);
   if (s != SCAN_SUCCESS) return s;
   const TwoPassKernels &K = kTwoPass;
   const int64_t tile = (int64_t)K.block * K.items;
@@ -497,6 +566,8 @@ scan_status_t compact(const void *in, void *out, int64_t n, scan_dtype_t dt, int
   DeviceInfo di;
   scan_status_t s = current_device(&dev, &di);
   if (s != SCAN_SUCCESS) return s;
+  s = stream_pending(dev, stream);
+  if (s != SCAN_SUCCESS) return s;
   // the partition kernels have their own shape; the n = 0 count kernel is the compaction's
   const CompactKernels &K = part ? kPartition : kCompact;
   if (n == 0) {
@@ -528,6 +599,7 @@ scan_status_t compact(const void *in, void *out, int64_t n, scan_dtype_t dt, int
     std::lock_guard<std::mutex> lk(g_mu);
     a.k.spin_limit = g_spin_limit;
   }
+  a.k.err = ws ? ws->err : nullptr;
   a.count = count;
   a.thr = threshold;
   a.pred = predicate;
@@ -570,7 +642,17 @@ struct GraphObj {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   Workspace ws;
+  uint32_t *err_host = nullptr;   // the graph's own error word
+  uint32_t *err_dev = nullptr;
 };
+
+void graph_free(GraphObj *g) {
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  ws_free(&g->ws);
+  err_free(&g->err_host, &g->err_dev);
+  delete g;
+}
 
 template <class Enqueue>
 scan_status_t capture(int64_t need_tiles, hipStream_t stream, Enqueue enqueue, void **out) {
@@ -581,16 +663,17 @@ scan_status_t capture(int64_t need_tiles, hipStream_t stream, Enqueue enqueue, v
   scan_status_t s = current_device(&dev, &di);
   if (s != SCAN_SUCCESS) return s;
   GraphObj *g = new GraphObj();
-  s = ws_alloc(&g->ws, dev, std::max<int64_t>(need_tiles, 2), stream);
+  s = err_alloc(&g->err_host, &g->err_dev);
+  if (s == SCAN_SUCCESS) s = ws_alloc(&g->ws, dev, std::max<int64_t>(need_tiles, 2), stream);
   if (s != SCAN_SUCCESS) {
-    delete g;
+    graph_free(g);
     return s;
   }
+  g->ws.err = g->err_dev;
   hipStream_t cs = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e != hipSuccess) {
-    ws_free(&g->ws);
-    delete g;
+    graph_free(g);
     return hip_fail(e);
   }
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -609,10 +692,7 @@ scan_status_t capture(int64_t need_tiles, hipStream_t stream, Enqueue enqueue, v
   }
   (void)hipStreamDestroy(cs);
   if (s != SCAN_SUCCESS) {
-    if (g->exec) (void)hipGraphExecDestroy(g->exec);
-    if (g->graph) (void)hipGraphDestroy(g->graph);
-    ws_free(&g->ws);
-    delete g;
+    graph_free(g);
     return s;
   }
   *out = g;
@@ -791,7 +871,10 @@ scan_status_t scan_release(hipStream_t stream) {
   if (it == g_ws.end()) return SCAN_SUCCESS;
   e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e);
-  ws_free(&it->second);
+  StreamState &ss = it->second;
+  ws_free(&ss.ws);
+  for (Workspace &w : ss.retired) ws_free(&w);
+  err_free(&ss.err_host, &ss.err_dev);
   g_ws.erase(it);
   return SCAN_SUCCESS;
 }
@@ -820,11 +903,15 @@ scan_status_t scan_looped_graph_create(const void *in, void *out, const int64_t 
                                        hipStream_t stream, void **graph) {
   if (num_segments < 0 || (num_segments > 0 && !host_offsets)) return SCAN_ERROR_INVALID_VALUE;
   ensure_init();
+  // tiles of the largest launch, sized with the pointers each launch gets
+  // (their alignment picks the kernel shape and so the tile size)
+  const char *pi = static_cast<const char *>(in);
+  char *po = static_cast<char *>(out);
   int64_t need = 2;
   for (int32_t s = 0; s < num_segments; ++s) {
-    const int64_t len = host_offsets[s + 1] - host_offsets[s];
+    const int64_t lo = host_offsets[s], len = host_offsets[s + 1] - lo;
     if (len > 0) {
-      Call c = make_call(in, out, len, dtype, false, flags, nullptr, 0);
+      Call c = make_call(pi + 4 * lo, po + 4 * lo, len, dtype, false, flags, nullptr, 0);
       need = std::max(need, call_tiles(c, select_config(c.opclass, false, len)));
     }
   }
@@ -838,18 +925,21 @@ scan_status_t scan_looped_graph_create(const void *in, void *out, const int64_t 
 scan_status_t scan_graph_launch(void *graph, hipStream_t stream) {
   if (!graph) return SCAN_ERROR_INVALID_VALUE;
   GraphObj *g = static_cast<GraphObj *>(graph);
+  if (take_error(g->err_host)) return SCAN_ERROR_TIMEOUT;   // an earlier replay gave up a wait
   hipError_t e = hipGraphLaunch(g->exec, stream);
   return e == hipSuccess ? SCAN_SUCCESS : hip_fail(e);
+}
+
+scan_status_t scan_graph_check_device_error(void *graph) {
+  if (!graph) return SCAN_ERROR_INVALID_VALUE;
+  return take_error(static_cast<GraphObj *>(graph)->err_host) ? SCAN_ERROR_TIMEOUT : SCAN_SUCCESS;
 }
 
 scan_status_t scan_graph_destroy(void *graph) {
   if (!graph) return SCAN_ERROR_INVALID_VALUE;
   GraphObj *g = static_cast<GraphObj *>(graph);
   (void)hipDeviceSynchronize();
-  if (g->exec) (void)hipGraphExecDestroy(g->exec);
-  if (g->graph) (void)hipGraphDestroy(g->graph);
-  ws_free(&g->ws);
-  delete g;
+  graph_free(g);
   return SCAN_SUCCESS;
 }
 
@@ -1000,23 +1090,9 @@ scan_status_t scan_check_device_error(hipStream_t stream) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, SCAN_ERROR_NOT_SUPPORTED);
-  WsHeader *hdr = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_ws.find(std::make_pair(dev, stream));
-    if (it != g_ws.end()) hdr = it->second.hdr;
-  }
   e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e);
-  if (!hdr) return SCAN_SUCCESS;
-  uint32_t err = 0;
-  e = hipMemcpy(&err, &hdr->error, sizeof(err), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(e);
-  if (!err) return SCAN_SUCCESS;
-  const uint32_t zero = 0;
-  e = hipMemcpy(&hdr->error, &zero, sizeof(zero), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e);
-  return SCAN_ERROR_TIMEOUT;
+  return stream_pending(dev, stream);
 }
 
 }  // extern "C"

@@ -125,6 +125,12 @@ __device__ __forceinline__ uint32_t ld_agent32(const uint32_t *p) {
 __device__ __forceinline__ void st_agent32(uint32_t *p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Raise the launch's error flag (a wait gave up).  The flag may be a word of
+// pinned host memory that the host polls without synchronising, hence the
+// system scope; it is written only on that rare path.
+__device__ __forceinline__ void raise_error(uint32_t *err) {
+  if (err) __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
 // ------------------------------------------------------------- wave (DPP) ops
 // DPP controls (GFX9 encoding): row_shr:k = 0x110+k, row_bcast:15 = 0x142,
@@ -224,7 +230,7 @@ __device__ __forceinline__ void lb_window(const uint64_t *st, int32_t base, uint
 // window w of base t-1.
 template <class Op, int K>
 __device__ typename Op::carry_t look_back(const uint64_t *st, int64_t t, uint32_t spin_limit,
-                                          WsHeader *hdr, uint64_t (&w)[K]) {
+                                          uint32_t *err, uint64_t (&w)[K]) {
   using carry_t = typename Op::carry_t;
   const int lane = (int)(opaque_tid() & 63u);
   carry_t acc = Op::czero();
@@ -259,7 +265,7 @@ __device__ typename Op::carry_t look_back(const uint64_t *st, int64_t t, uint32_
     }
     if (wait) {
       if (++spins > spin_limit) {
-        if (lane == 0) st_agent32(&hdr->error, 1u);
+        if (lane == 0) raise_error(err);
         return acc;
       }
       __builtin_amdgcn_s_sleep(1);
@@ -855,7 +861,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
       if (need_carry) {
         uint64_t w[K];
         lb_window<Op, K>(st, (int32_t)t - 1, w);
-        carry = look_back<Op, K>(st, t, a.spin_limit, a.hdr, w);
+        carry = look_back<Op, K>(st, t, a.spin_limit, a.err, w);
         if (!aggf && lane == 0)
           st_agent(st + t, Op::pack(Op::canon(Op::cadd(carry, Op::canon(agg))), kPrefix));
       }
@@ -912,12 +918,16 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
             c = readlane32(wave_scan<OpsU32>(c), 63);
             if ((int64_t)c >= a.tiles - 1) break;
             if (spins > a.spin_limit) {
-              if (lane == 0) st_agent32(&a.hdr->error, 1u);
+              if (lane == 0) raise_error(a.err);
               break;
             }
             __builtin_amdgcn_s_sleep(1);
           }
-          // the next launch uses the other parity's counters
+          // every increment of this launch has landed: leave both parities'
+          // counters at zero, so the next ordered launch on either parity
+          // starts from zero whatever ran in between (other modes never
+          // touch them)
+          st_agent(a.pubcnt + (parity * kPubSlots + l) * kPubStride, 0ull);
           st_agent(a.pubcnt + ((1 - parity) * kPubSlots + l) * kPubStride, 0ull);
         }
         __syncthreads();

@@ -21,7 +21,7 @@ constexpr uint32_t kPrefix = 2;  // value = inclusive prefix through this tile
 // reset kernel is needed between launches, also inside graphs.
 struct alignas(64) WsHeader {
   uint32_t parity;
-  uint32_t error;        // set when a wait exceeds its spin limit
+  uint32_t error;        // error word of the no-allocation scratch workspace
   uint64_t dirty[2];     // words of status array q that may be non-zero
   uint64_t counter[2];   // tile counters, one per status array
   uint64_t reserved[2];
@@ -41,6 +41,7 @@ struct KernelArgs {
   const uint32_t *tile_seg;   // segmented: first segment per tile boundary (T+1), or null if T == 1
   int64_t num_segments;
   uint32_t spin_limit;
+  uint32_t *err;              // set to 1 when a wait exceeds spin_limit (host-visible word)
   uint32_t exclusive;
   uint32_t reverse;
   uint32_t one_tile;          // every workgroup takes exactly one tile

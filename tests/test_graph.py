@@ -119,3 +119,59 @@ def test_capture_of_flat_scan_after_reserve():
         g.replay()
         torch.cuda.synchronize()
         assert not first_mismatch(out.cpu().numpy().view(np.uint32), want)
+
+
+def test_captured_graph_survives_workspace_growth():
+    """A graph captured from library calls keeps its workspace when a later,
+    larger eager call on the same stream grows the stream's workspace."""
+    import paper_2312_14874_amd as scan
+    n = 3_000_000
+    a = workloads.full_u32(n, seed=15)
+    x = to_dev(a)
+    out = torch.empty_like(x)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        scan.reserve(n)
+        scan.cumsum(x, out=out)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        scan.cumsum(x, out=out)
+    want = oracle.scan_int(a)
+    # an eager call needing many more tiles than reserved: 4096-element tiles
+    big = workloads.full_u32(16 * n, seed=16)
+    xb = to_dev(big)
+    yb = torch.empty_like(xb)
+    scan.force_config(11)
+    try:
+        with torch.cuda.stream(s):
+            scan.cumsum(xb, out=yb)
+    finally:
+        scan.force_config(-1)
+    torch.cuda.synchronize()
+    assert not first_mismatch(yb.cpu().numpy().view(np.uint32), oracle.scan_int(big))
+    for _ in range(3):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert not first_mismatch(out.cpu().numpy().view(np.uint32), want)
+        with torch.cuda.stream(s):
+            scan.cumsum(xb, out=yb)        # eager work on the grown workspace in between
+        torch.cuda.synchronize()
+    assert not first_mismatch(yb.cpu().numpy().view(np.uint32), oracle.scan_int(big))
+
+
+def test_looped_graph_with_misaligned_segments():
+    """Segments whose start is not 16-byte aligned take the dword kernel's
+    smaller tiles: the graph's workspace is sized for those."""
+    import paper_2312_14874_amd as scan
+    for off in (np.array([0, 3, 20003], dtype=np.int64), np.array([0, 1, 5, 70_006, 70_007], dtype=np.int64)):
+        n = int(off[-1])
+        a = workloads.full_u32(n, seed=n)
+        x = to_dev(a)
+        out = torch.empty_like(x)
+        gl = scan.LoopedScanGraph(x, out, off, exclusive=True)
+        gl.launch()
+        torch.cuda.synchronize()
+        assert not first_mismatch(out.cpu().numpy().view(np.uint32), oracle.segmented_int(a, off, exclusive=True))
+        gl.close()
