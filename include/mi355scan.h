@@ -126,6 +126,31 @@ scan_status_t scan_exclusive_f32(const float *in, float *out, int64_t n, hipStre
 scan_status_t scan_flat(const void *in, void *out, int64_t n, scan_dtype_t dtype,
                         uint32_t flags, hipStream_t stream);
 
+/* ---- allocation-free flat scan ----
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Computes
+ * exactly what scan_flat computes for the 32-bit dtypes (SCAN_I32 / SCAN_U32
+ * / SCAN_F32, every flag and operator scan_flat accepts for them), but its
+ * tile status words, counters and error word live in a fixed array of the
+ * library in device memory (one copy per device, 540,736 bytes, zero when
+ * the library loads, held until the process ends) instead of a stream
+ * workspace, and the call makes no allocation of any kind (no hipMalloc,
+ * hipFree or hipHostMalloc; the first call on a device only looks up that
+ * device's copy of the array).  Arguments and results are scan_flat's.
+ * Limit: 32768 tiles, i.e. n <= 3,221,225,472 when in and out are 16-byte
+ * aligned (98,304-element tiles at most) and n <= 268,435,456 otherwise
+ * (8,192-element tiles); a larger n returns SCAN_ERROR_INVALID_VALUE, a
+ * 64-bit dtype SCAN_ERROR_NOT_SUPPORTED, both before anything is enqueued.
+ * Every call on one device shares that device's array, and each call leaves
+ * it clean for the next: calls whose kernels overlap in time on one device
+ * (two streams, two host threads) race and give wrong results, so keep them
+ * on one stream.  A device-side wait that gives up raises the array's error
+ * word; scan_check_device_error (with that device current, any stream)
+ * reports and clears it.  Graphs captured from these calls stay valid for
+ * the life of the process. */
+scan_status_t scan_flat_noalloc(const void *in, void *out, int64_t n, scan_dtype_t dtype,
+                                uint32_t flags, hipStream_t stream);
+
 /* ---- batched segmented scan (one persistent launch) ----
  * Scans num_segments independent segments of one concatenated array: segment
  * s covers in[offsets[s] .. offsets[s+1]), and each segment's result is the
@@ -299,8 +324,9 @@ int32_t       scan_last_hip_error(void);
  * call are then invalid).  Applies to launches enqueued (or graphs created)
  * after the call. */
 scan_status_t scan_set_spin_limit(uint32_t limit);
-/* Synchronise `stream`, read and clear its error word: SCAN_SUCCESS or
- * SCAN_ERROR_TIMEOUT. */
+/* Synchronise `stream`, read and clear its error word, and the error word of
+ * the current device's scan_flat_noalloc array once a call has used it:
+ * SCAN_SUCCESS, or SCAN_ERROR_TIMEOUT if either was raised. */
 scan_status_t scan_check_device_error(hipStream_t stream);
 
 #ifdef __cplusplus

@@ -21,6 +21,21 @@
 #include "scan_table.hpp"
 #include "validate.hpp"
 
+// Workspace of scan_flat_noalloc, the entry point for callers that cannot
+// allocate: a library array in device memory (one copy per device, zero at
+// module load, held until the process ends) laid out as a stream workspace
+// without tile map and two-pass sums: header | publish counters |
+// status[2][kScratchTiles].  The kernels raise the header's `error` word on a
+// timeout.  In host code `scratch` only names the symbol: its device address
+// comes from hipGetSymbolAddress (per device, see scratch_ws).
+namespace mi355scan {
+constexpr int64_t kScratchTiles = int64_t(1) << 15;
+constexpr size_t kScratchBytes =
+    sizeof(WsHeader) + kPubWords * sizeof(uint64_t) + (size_t)kScratchTiles * 2 * sizeof(uint64_t);
+static_assert(kScratchBytes % sizeof(uint64_t) == 0, "scratch layout");
+}  // namespace mi355scan
+static __device__ __align__(256) uint64_t scratch[mi355scan::kScratchBytes / sizeof(uint64_t)];
+
 namespace mi355scan {
 namespace {
 
@@ -166,6 +181,38 @@ struct StreamState {
   uint32_t *err_dev = nullptr;
 };
 std::map<std::pair<int, hipStream_t>, StreamState> g_ws;
+
+// The allocation-free workspace of each device: the device address of that
+// device's copy of `scratch`, taken once with the device current.
+std::map<int, Workspace> g_scratch;
+
+scan_status_t scratch_ws(int device, Workspace **out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_scratch.find(device);
+  if (it == g_scratch.end()) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e == hipSuccess ? hipErrorInvalidSymbol : e);
+    Workspace w;
+    w.device = device;
+    w.base = static_cast<char *>(p);
+    w.hdr = reinterpret_cast<WsHeader *>(w.base);
+    w.pubcnt = reinterpret_cast<uint64_t *>(w.base + sizeof(WsHeader));
+    w.status = reinterpret_cast<uint64_t *>(w.base + kStatusOffset);
+    w.err = &w.hdr->error;
+    w.capacity = kScratchTiles;
+    it = g_scratch.emplace(device, w).first;
+  }
+  *out = &it->second;
+  return SCAN_SUCCESS;
+}
+
+// The scratch workspace of `device` if a call has set it up, else null.
+Workspace *scratch_ws_if_set(int device) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_scratch.find(device);
+  return it == g_scratch.end() ? nullptr : &it->second;
+}
 
 // A timeout raised by an earlier launch on this stream is reported (once) by
 // the next call, which then enqueues nothing: its results could not be told
@@ -472,6 +519,32 @@ scan_status_t flat(const void *in, void *out, int64_t n, scan_dtype_t dt, uint32
   ensure_init();
   Call c = make_call(in, out, n, dt, false, flags, nullptr, 0);
   return launch(c, stream, nullptr, -1);
+}
+
+// Flat 32-bit scan on the device's scratch workspace: the tuned
+// configuration when its tiles fit the scratch, else the default one (the
+// largest tiles), else the call is refused.  Nothing is allocated.
+scan_status_t flat_noalloc(const void *in, void *out, int64_t n, scan_dtype_t dt, uint32_t flags,
+                           hipStream_t stream) {
+  int r = check_dtype((int)dt);
+  if (r == kOk) r = check_flags(flags);
+  if (r == kOk) r = check_flat(in, out, n);
+  if (r == kOk) r = check_operator((int)dt, flags);
+  if (r != kOk) return st(r);
+  if (n == 0) return SCAN_SUCCESS;
+  ensure_init();
+  Call c = make_call(in, out, n, dt, false, flags, nullptr, 0);
+  int cfg = select_config(c.opclass, false, n);
+  if (call_tiles(c, cfg) > kScratchTiles) cfg = kDefaultFlatConfig;
+  if (call_tiles(c, cfg) > kScratchTiles) return SCAN_ERROR_INVALID_VALUE;
+  int dev = 0;
+  DeviceInfo di;
+  scan_status_t s = current_device(&dev, &di);
+  if (s != SCAN_SUCCESS) return s;
+  Workspace *ws = nullptr;
+  s = scratch_ws(dev, &ws);
+  if (s != SCAN_SUCCESS) return s;
+  return launch(c, stream, ws, cfg);
 }
 
 scan_status_t segmented(const void *in, void *out, const int64_t *offsets, int32_t S, int64_t n,
@@ -803,6 +876,11 @@ scan_status_t scan_flat(const void *in, void *out, int64_t n, scan_dtype_t dtype
   return flat(in, out, n, dtype, flags, stream);
 }
 
+scan_status_t scan_flat_noalloc(const void *in, void *out, int64_t n, scan_dtype_t dtype, uint32_t flags,
+                                hipStream_t stream) {
+  return flat_noalloc(in, out, n, dtype, flags, stream);
+}
+
 scan_status_t scan_inclusive_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s) {
   return flat(in, out, n, SCAN_I32, 0u, s);
 }
@@ -1092,7 +1170,21 @@ scan_status_t scan_check_device_error(hipStream_t stream) {
   if (e != hipSuccess) return hip_fail(e, SCAN_ERROR_NOT_SUPPORTED);
   e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e);
-  return stream_pending(dev, stream);
+  scan_status_t s = stream_pending(dev, stream);
+  // the device's allocation-free workspace (scan_flat_noalloc), if set up:
+  // its error word is device memory, read and cleared by plain copies
+  if (Workspace *sw = scratch_ws_if_set(dev)) {
+    uint32_t v = 0u;
+    e = hipMemcpy(&v, &sw->hdr->error, sizeof(v), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e);
+    if (v) {
+      const uint32_t zero = 0u;
+      e = hipMemcpy(&sw->hdr->error, &zero, sizeof(zero), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(e);
+      s = SCAN_ERROR_TIMEOUT;
+    }
+  }
+  return s;
 }
 
 }  // extern "C"

@@ -55,9 +55,38 @@ def test_flat_argument_errors(args, code):
     assert L.lib.scan_flat(*args, None) == code
 
 
+@pytest.mark.parametrize("args,code", [
+    ((None, None, 10, 0, 0), INVALID),          # null pointers
+    ((4096, 8192, 10, 0, 0x10), INVALID),       # unknown flag
+    ((4096, 4100, 10, 0, 0), OVERLAP),          # partial overlap
+    ((4096, 1 << 20, 10, 3, 0), 5),             # 64-bit dtypes: not offered without allocation
+    ((4096, 1 << 20, 10, 2, 0x4), 5),           # max of float32
+])
+def test_noalloc_argument_errors(args, code):
+    L = _lib()
+    assert L.lib.scan_flat_noalloc(*args, None) == code
+
+
+# The allocation-free scan holds 32768 tiles: 98,304-element tiles at most for
+# 16-byte aligned buffers, 8,192-element tiles otherwise.
+NOALLOC_MAX_ALIGNED = 32768 * 98304
+NOALLOC_MAX_UNALIGNED = 32768 * 8192
+
+
+@pytest.mark.parametrize("n,misalign", [(NOALLOC_MAX_ALIGNED + 1, 0), (NOALLOC_MAX_UNALIGNED + 1, 4),
+                                        (1 << 40, 0)])
+def test_noalloc_rejects_sizes_beyond_its_array(n, misalign):
+    # refused on the host before any device call (none is made here: no GPU)
+    L = _lib()
+    a = (1 << 44) + misalign
+    assert L.lib.scan_flat_noalloc(a, a + (1 << 45), n, 1, 0, None) == INVALID
+    assert L.lib.scan_flat_noalloc(a, a, n, 2, 1, None) == INVALID
+
+
 def test_zero_length_is_noop():
     L = _lib()
     assert L.lib.scan_flat(None, None, 0, 0, 0, None) == 0
+    assert L.lib.scan_flat_noalloc(None, None, 0, 0, 0, None) == 0
     assert L.lib.scan_inclusive_i32(None, None, 0, None) == 0
     assert L.lib.scan_segmented_batch(None, None, None, 0, 0, 0, 0, None) == 0
 
