@@ -324,6 +324,19 @@ int32_t       scan_last_hip_error(void);
  * call are then invalid).  Applies to launches enqueued (or graphs created)
  * after the call. */
 scan_status_t scan_set_spin_limit(uint32_t limit);
+/* Streaming ceiling of the scan's memory access pattern (measurement, not a
+ * scan): out[i] = in[i] + 1 modulo 2^32 for n 32-bit elements, with the tile
+ * shape, grid, tile counter, 128-bit buffer accesses, cache policy and
+ * store/load hand-off of scan configuration `config` (scan_config_info;
+ * counter modes 0 and 1 only, others return SCAN_ERROR_NOT_SUPPORTED), but
+ * without the in-register scan and the look-back.  It moves the scan's 8
+ * bytes per element, the two-words-per-element floor that the partitioned
+ * scan of Section 2.2 reaches, so its time is the floor of the scan kernel of
+ * that shape.  in and out must be 16-byte aligned (SCAN_ERROR_INVALID_VALUE
+ * otherwise); in == out is allowed.  Uses the stream's workspace (tile
+ * counter). */
+scan_status_t scan_stream_ceiling(const void *in, void *out, int64_t n, int32_t config, hipStream_t stream);
+
 /* Synchronise `stream`, read and clear its error word, and the error word of
  * the current device's scan_flat_noalloc array once a call has used it:
  * SCAN_SUCCESS, or SCAN_ERROR_TIMEOUT if either was raised. */

@@ -43,6 +43,7 @@ SIGNATURES = {
     "scan_exclusive_f32": (ST, [P, P, I64, P]),
     "scan_flat": (ST, [P, P, I64, ST, U32, P]),
     "scan_flat_noalloc": (ST, [P, P, I64, ST, U32, P]),
+    "scan_stream_ceiling": (ST, [P, P, I64, I32, P]),
     "scan_segmented_batch": (ST, [P, P, P, I32, I64, ST, U32, P]),
     "scan_two_pass": (ST, [P, P, I64, ST, U32, I32, I64, P]),
     "scan_compact": (ST, [P, P, I64, ST, I32, U32, P, P]),

@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
       if (t > 0) {
         uint64_t w[K];
         lb_window<Op, K>(st, (int32_t)t - 1, w);
-        carry = look_back<Op, K>(st, t, ka.spin_limit, ka.err, w);
+        carry = look_back<Op, K, K>(st, t, ka.spin_limit, ka.err, w);
         if (lane == 0) st_agent(st + t, Op::pack(carry + agg, kPrefix));
       }
       if (lane == 0) s_carry = carry;

@@ -43,7 +43,13 @@ namespace {
 // 2^30 elements); 2^16 sleeping polls is of the order of 0.1 s.
 constexpr uint32_t kDefaultSpinLimit = 1u << 16;
 constexpr int kDefaultFlatConfig = 22;  // 768 threads x 128 items, one resident workgroup per CU
-constexpr int kDefaultSegConfig = 4;    // 256 threads x 128 items, tile = workgroup index
+constexpr int kDefaultSegConfig = 20;   // 512 threads x 128 items, one resident workgroup per CU
+// The autotuner takes a configuration whose tile order relies on the
+// dispatcher (mode 2: tile = workgroup index, in-order dispatch assumed) or
+// on co-residency (mode 4) only when it beats the best counter-mode
+// configuration by more than this fraction; otherwise timing noise would
+// decide between them.
+constexpr float kOrderedMargin = 0.03f;
 constexpr int kBuckets = 64;
 
 thread_local int t_last_hip = 0;
@@ -521,6 +527,54 @@ scan_status_t flat(const void *in, void *out, int64_t n, scan_dtype_t dt, uint32
   return launch(c, stream, nullptr, -1);
 }
 
+// The streaming-ceiling kernel (stream_ceiling.hpp) with the tile shape,
+// grid and tile counter of configuration cfg (counter modes only).
+scan_status_t stream_ceiling(const void *in, void *out, int64_t n, int32_t cfg, hipStream_t stream) {
+  const int r = check_flat(in, out, n);
+  if (r != kOk) return st(r);
+  if (cfg < 0 || cfg >= kNumConfigs) return SCAN_ERROR_INVALID_VALUE;
+  if (((uintptr_t)in | (uintptr_t)out) & 15u) return SCAN_ERROR_INVALID_VALUE;
+  const Config &cf = kConfigs[cfg];
+  if (cf.mode != kModeCounter && cf.mode != kModePersistent) return SCAN_ERROR_NOT_SUPPORTED;
+  if (n == 0) return SCAN_SUCCESS;
+  ensure_init();
+  int dev = 0;
+  DeviceInfo di;
+  scan_status_t s = current_device(&dev, &di);
+  if (s != SCAN_SUCCESS) return s;
+  s = stream_pending(dev, stream);
+  if (s != SCAN_SUCCESS) return s;
+  const KernelShape &sh = kShapes[cf.shape];
+  const int64_t T = tiles_for(n, (int64_t)sh.block * sh.items);
+  if (T > kMaxTiles) return SCAN_ERROR_NOT_SUPPORTED;
+  Workspace *ws = nullptr;
+  if (T > 1) {
+    s = stream_ws(dev, stream, T, &ws);
+    if (s != SCAN_SUCCESS) return s;
+  }
+  KernelArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.in = in;
+  a.out = out;
+  a.n = n;
+  a.tiles = T;
+  a.hdr = ws ? ws->hdr : nullptr;
+  a.status = ws ? ws->status : nullptr;
+  a.capacity = ws ? ws->capacity : 0;
+  a.err = ws ? ws->err : nullptr;
+  int64_t grid = T;
+  a.one_tile = 1u;
+  a.total_acquires = (uint64_t)T;
+  if (T > 1 && cf.mode != kModeCounter) {
+    grid = std::min<int64_t>(T, resident_grid(sh.copy, sh.block, di.cus, cf.per_cu, cf.cu_pct));
+    a.one_tile = grid == T ? 1u : 0u;
+    a.total_acquires = a.one_tile ? (uint64_t)T : (uint64_t)(T + grid);
+  }
+  void *args[] = {&a};
+  hipError_t e = hipLaunchKernel(sh.copy, dim3((unsigned)grid), dim3(sh.block), args, 0, stream);
+  return e == hipSuccess ? SCAN_SUCCESS : hip_fail(e);
+}
+
 // Flat 32-bit scan on the device's scratch workspace: the tuned
 // configuration when its tiles fit the scratch, else the default one (the
 // largest tiles), else the call is refused.  Nothing is allocated.
@@ -876,6 +930,10 @@ scan_status_t scan_flat(const void *in, void *out, int64_t n, scan_dtype_t dtype
   return flat(in, out, n, dtype, flags, stream);
 }
 
+scan_status_t scan_stream_ceiling(const void *in, void *out, int64_t n, int32_t config, hipStream_t stream) {
+  return stream_ceiling(in, out, n, config, stream);
+}
+
 scan_status_t scan_flat_noalloc(const void *in, void *out, int64_t n, scan_dtype_t dtype, uint32_t flags,
                                 hipStream_t stream) {
   return flat_noalloc(in, out, n, dtype, flags, stream);
@@ -1076,8 +1134,8 @@ scan_status_t scan_autotune(const void *in, void *out, int64_t n, const int64_t 
     return hip_fail(e);
   }
   Call c = make_call(in, out, n, dtype, seg, flags, offsets, num_segments);
-  float best_ms = 1e30f;
-  int best_cfg = -1;
+  float best_ms = 1e30f, best_dyn_ms = 1e30f;
+  int best_cfg = -1, best_dyn = -1;
   scan_status_t s = SCAN_SUCCESS;
   for (int cfg = 0; cfg < kNumConfigs && s == SCAN_SUCCESS; ++cfg) {
     std::vector<float> times;
@@ -1098,7 +1156,14 @@ scan_status_t scan_autotune(const void *in, void *out, int64_t n, const int64_t 
       best_ms = med;
       best_cfg = cfg;
     }
+    const int mode = kConfigs[cfg].mode;
+    if ((mode == kModeCounter || mode == kModePersistent) && med < best_dyn_ms) {
+      best_dyn_ms = med;
+      best_dyn = cfg;
+    }
   }
+  if (best_dyn >= 0 && best_cfg != best_dyn && !(best_ms < best_dyn_ms * (1.0f - kOrderedMargin)))
+    best_cfg = best_dyn;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (s != SCAN_SUCCESS) return s;

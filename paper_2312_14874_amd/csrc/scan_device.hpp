@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "scan_shared.hpp"
 
 namespace mi355scan {
@@ -193,6 +195,13 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
 }
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// A wave-uniform copy of lane l's value (32- or 64-bit).
+template <class T>
+__device__ __forceinline__ T readlane_of(T x, int l) {
+  if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, readlane64(__builtin_bit_cast(uint64_t, x), l));
+  else return __builtin_bit_cast(T, readlane32(__builtin_bit_cast(uint32_t, x), l));
+}
+
 // The thread index as a value the compiler cannot see through: per-lane
 // addresses built from it at a use site stay there instead of being hoisted
 // out of the tile loop, where they would hold registers (or spill) for the
@@ -213,88 +222,112 @@ __device__ __forceinline__ uint32_t opaque_tid() {
 // the PREFIX is in the window so that the fold order is always the canonical
 // left-to-right chain.
 
-// Issue the loads of one window (indices below 0 read as an empty PREFIX).
-// Tile indices are below 2^30 (checked by the host), so they and the byte
-// offsets into the status array fit in 32 bits.
+// Issue the loads of one window.  Every lane loads (an index below 0 reads
+// tile 0's word, which lb_examine replaces by an empty PREFIX), so no
+// instruction consumes the loaded words before they are examined and their
+// round trip can overlap other work.  Tile indices are below 2^30 (checked by
+// the host), so they and the byte offsets into the status array fit in 32
+// bits.
 template <class Op, int K>
 __device__ __forceinline__ void lb_window(const uint64_t *st, int32_t base, uint64_t (&w)[K]) {
   const int lane = (int)(opaque_tid() & 63u);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int32_t idx = base - (64 * k + lane);
-    w[k] = idx >= 0 ? ld_agent(st + (uint32_t)idx) : Op::pack(Op::czero(), kPrefix);
+    w[k] = ld_agent(st + (uint32_t)(idx >= 0 ? idx : 0));
   }
 }
 
-// Exclusive carry into tile t (t >= 1), starting from an already issued
-// window w of base t-1.
-template <class Op, int K>
-__device__ typename Op::carry_t look_back(const uint64_t *st, int64_t t, uint32_t spin_limit,
-                                          uint32_t *err, uint64_t (&w)[K]) {
+// What one examined window decided.
+enum LbStep { kLbDone = 0, kLbWait = 1, kLbMove = 2 };
+
+// Examine window w of base `base`: kLbDone with the carry in `out`, kLbWait
+// (a needed word is still EMPTY, or a float window holds no PREFIX yet), or
+// kLbMove (integers: a full window of aggregates was added to acc and base
+// moved back past it).
+template <class Op, int KW>
+__device__ __forceinline__ int lb_examine(uint64_t (&w)[KW], int32_t &base, typename Op::carry_t &acc,
+                                          typename Op::carry_t &out) {
   using carry_t = typename Op::carry_t;
   const int lane = (int)(opaque_tid() & 63u);
-  carry_t acc = Op::czero();
-  int32_t base = (int32_t)t - 1;
-  uint32_t spins = 0;
   constexpr int kNone = 1 << 30;
-  for (bool fresh = true;; fresh = false) {
-    if (!fresh) lb_window<Op, K>(st, base, w);
-    int dP = kNone, dE = kNone;
+  // predecessors before tile 0: an empty prefix
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const uint32_t f = Op::flag_of(w[k]);
-      const uint64_t bP = ballot(f == kPrefix);
-      const uint64_t bE = ballot(f == kEmpty);
-      if (dP == kNone && bP) dP = 64 * k + __builtin_ctzll(bP);
-      if (dE == kNone && bE) dE = 64 * k + __builtin_ctzll(bE);
-    }
-    bool wait = dE < dP;
-    if (!wait && dP == kNone) {
-      if constexpr (Op::kExact) {
-        // a full window of aggregates: add them all and move further back
-        carry_t part = Op::czero();
+  for (int k = 0; k < KW; ++k)
+    if (base - (64 * k + lane) < 0) w[k] = Op::pack(Op::czero(), kPrefix);
+  int dP = kNone, dE = kNone;
 #pragma unroll
-        for (int k = 0; k < K; ++k) part = Op::cadd(part, Op::value_of(w[k]));
-        part = Op::narrow(readlane32(Op::lbits(wave_scan<Op>(part)), 63));
-        acc = Op::cadd(acc, part);
-        base -= 64 * K;
-        continue;
-      } else {
-        wait = true;
-      }
+  for (int k = 0; k < KW; ++k) {
+    const uint32_t f = Op::flag_of(w[k]);
+    const uint64_t bP = ballot(f == kPrefix);
+    const uint64_t bE = ballot(f == kEmpty);
+    if (dP == kNone && bP) dP = 64 * k + __builtin_ctzll(bP);
+    if (dE == kNone && bE) dE = 64 * k + __builtin_ctzll(bE);
+  }
+  if (dE < dP) return kLbWait;
+  if (dP == kNone) {
+    if constexpr (Op::kExact) {
+      // a full window of aggregates: add them all and move further back
+      carry_t part = Op::czero();
+#pragma unroll
+      for (int k = 0; k < KW; ++k) part = Op::cadd(part, Op::value_of(w[k]));
+      part = Op::narrow(readlane32(Op::lbits(wave_scan<Op>(part)), 63));
+      acc = Op::cadd(acc, part);
+      base -= 64 * KW;
+      return kLbMove;
+    } else {
+      return kLbWait;
     }
-    if (wait) {
+  }
+  if constexpr (Op::kExact) {
+    carry_t part = Op::czero();
+#pragma unroll
+    for (int k = 0; k < KW; ++k)
+      if (64 * k + lane <= dP) part = Op::cadd(part, Op::value_of(w[k]));
+    part = Op::narrow(readlane32(Op::lbits(wave_scan<Op>(part)), 63));
+    out = Op::cadd(acc, part);
+  } else {
+    // left fold from the PREFIX at distance dP down to distance 0; the
+    // window index k is kept static so no private array is indexed
+    // dynamically
+    carry_t c = Op::czero();
+#pragma unroll
+    for (int k = 0; k < KW; ++k)
+      if (k == (dP >> 6)) c = Op::value_of(readlane64(w[k], dP & 63));
+#pragma unroll
+    for (int k = KW - 1; k >= 0; --k) {
+      int l = dP - 1 - 64 * k;
+      if (l > 63) l = 63;
+      for (; l >= 0; --l) c = Op::canon(Op::cadd(c, Op::value_of(readlane64(w[k], l))));
+    }
+    out = c;
+  }
+  return kLbDone;
+}
+
+// Exclusive carry into tile t (t >= 1), starting from an already issued
+// window w1 of base t-1 (64*K1 tiles); later polls read 64*K tiles each.
+template <class Op, int K1, int K>
+__device__ typename Op::carry_t look_back(const uint64_t *st, int64_t t, uint32_t spin_limit,
+                                          uint32_t *err, uint64_t (&w1)[K1]) {
+  using carry_t = typename Op::carry_t;
+  carry_t acc = Op::czero(), out = Op::czero();
+  int32_t base = (int32_t)t - 1;
+  int r = lb_examine<Op, K1>(w1, base, acc, out);
+  uint32_t spins = 0;
+  while (r != kLbDone) {
+    if (r == kLbWait) {
       if (++spins > spin_limit) {
-        if (lane == 0) raise_error(err);
+        if ((opaque_tid() & 63u) == 0) raise_error(err);
         return acc;
       }
       __builtin_amdgcn_s_sleep(1);
-      continue;
     }
-    if constexpr (Op::kExact) {
-      carry_t part = Op::czero();
-#pragma unroll
-      for (int k = 0; k < K; ++k)
-        if (64 * k + lane <= dP) part = Op::cadd(part, Op::value_of(w[k]));
-      part = Op::narrow(readlane32(Op::lbits(wave_scan<Op>(part)), 63));
-      return Op::cadd(acc, part);
-    } else {
-      // left fold from the PREFIX at distance dP down to distance 0; the
-      // window index k is kept static so no private array is indexed
-      // dynamically
-      carry_t c = Op::czero();
-#pragma unroll
-      for (int k = 0; k < K; ++k)
-        if (k == (dP >> 6)) c = Op::value_of(readlane64(w[k], dP & 63));
-#pragma unroll
-      for (int k = K - 1; k >= 0; --k) {
-        int l = dP - 1 - 64 * k;
-        if (l > 63) l = 63;
-        for (; l >= 0; --l) c = Op::canon(Op::cadd(c, Op::value_of(readlane64(w[k], l))));
-      }
-      return c;
-    }
+    uint64_t w[K];
+    lb_window<Op, K>(st, base, w);
+    r = lb_examine<Op, K>(w, base, acc, out);
   }
+  return out;
 }
 
 // Tile addressing.  Logical element e of a tile is physical pb+e going
@@ -496,20 +529,25 @@ __device__ __forceinline__ void load_tile(const KernelArgs &a, int64_t t, int wa
   for (int c = 0; c < SH::CH; ++c) in.load(c, R[c]);
 }
 
-// One chunk of scan_wave without a segment start: in-lane inclusive
-// partials, the wave scan of the lane totals, then the chunk's prefix within
-// the wave (uniform, wsum; none for the first chunk) joins the lane's
-// offset; inclusive: off + p_k, exclusive: off + p_{k-1}, chosen by selects
-// so every chunk stays in its own registers.  wsum grows by the chunk total.
+// One chunk of scan_wave without a segment start, in two steps.
+// chunk_lane: in-lane inclusive partials of the lane's 4-group (keyed first).
 template <class Op, bool REV>
-__device__ __forceinline__ void plain_chunk(u32x4 &r, typename Op::carry_t &wsum, bool ex, bool first,
-                                            uint32_t key) {
-  using lane_t = typename Op::lane_t;
+__device__ __forceinline__ void chunk_lane(u32x4 &r, uint32_t key) {
   constexpr int p0 = REV ? 3 : 0, p1 = REV ? 2 : 1, p2 = REV ? 1 : 2, p3 = REV ? 0 : 3;
   constexpr int ph[4] = {p0, p1, p2, p3};
   if constexpr (Op::kKeyed) r ^= key;
 #pragma unroll
   for (int k = 1; k < 4; ++k) r[ph[k]] = Op::lbits(Op::ladd(Op::lfrom(r[ph[k - 1]]), Op::lfrom(r[ph[k]])));
+}
+
+// chunk_wave: the wave scan of the lane totals, then the chunk's prefix
+// within the wave (uniform, wsum; none for the first chunk) joins the lane's
+// offset; inclusive: off + p_k, exclusive: off + p_{k-1}, chosen by selects
+// so every chunk stays in its own registers.  wsum grows by the chunk total.
+template <class Op, bool REV>
+__device__ __forceinline__ void chunk_wave(u32x4 &r, typename Op::carry_t &wsum, bool ex, bool first) {
+  using lane_t = typename Op::lane_t;
+  constexpr int p0 = REV ? 3 : 0, p1 = REV ? 2 : 1, p2 = REV ? 1 : 2, p3 = REV ? 0 : 3;
   const lane_t x = wave_scan<Op>(Op::lfrom(r[p3]));
   const lane_t lex = Op::lfrom(lane_up1(Op::lbits(x)));   // lane-exclusive value in the chunk
   const lane_t ct = Op::lfrom(readlane32(Op::lbits(x), 63));
@@ -524,6 +562,37 @@ __device__ __forceinline__ void plain_chunk(u32x4 &r, typename Op::carry_t &wsum
   // per element), keeping one offset register per chunk alive through the
   // look-back
   asm volatile("" : "+v"(r));
+}
+
+template <class Op, bool REV>
+__device__ __forceinline__ void plain_chunk(u32x4 &r, typename Op::carry_t &wsum, bool ex, bool first,
+                                            uint32_t key) {
+  chunk_lane<Op, REV>(r, key);
+  chunk_wave<Op, REV>(r, wsum, ex, first);
+}
+
+// Total over the 64 lanes of a carry-type value (float64 for OpsF32: both
+// halves move through the same DPP row shifts and broadcasts as wave_scan),
+// in a fixed order; wave-uniform.
+template <class Op>
+__device__ __forceinline__ typename Op::carry_t wave_total(typename Op::carry_t x) {
+  if constexpr (sizeof(typename Op::carry_t) == 4) {
+    return Op::widen(Op::lfrom(readlane32(Op::lbits(wave_scan<Op>(Op::narrow(x))), 63)));
+  } else {
+    auto step = [](typename Op::carry_t v, auto ctrl_tag, auto mask_tag) {
+      constexpr int CTRL = decltype(ctrl_tag)::value, MASK = decltype(mask_tag)::value;
+      const uint64_t b = __builtin_bit_cast(uint64_t, v);
+      const uint64_t s = ((uint64_t)dpp<CTRL, MASK>((uint32_t)(b >> 32)) << 32) | dpp<CTRL, MASK>((uint32_t)b);
+      return Op::cadd(__builtin_bit_cast(typename Op::carry_t, s), v);
+    };
+    x = step(x, std::integral_constant<int, 0x111>{}, std::integral_constant<int, 0xf>{});
+    x = step(x, std::integral_constant<int, 0x112>{}, std::integral_constant<int, 0xf>{});
+    x = step(x, std::integral_constant<int, 0x114>{}, std::integral_constant<int, 0xf>{});
+    x = step(x, std::integral_constant<int, 0x118>{}, std::integral_constant<int, 0xf>{});
+    x = step(x, std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xa>{});
+    x = step(x, std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xc>{});
+    return readlane_of(x, 63);
+  }
 }
 
 // In-register scan of this wave's span (the 64-lane form of the horizontal
@@ -647,12 +716,6 @@ __device__ __forceinline__ void scan_wave(uint32_t exclusive, uint32_t key, int 
   wflag_out = wflag;
 }
 
-// A wave-uniform copy of lane l's value (32- or 64-bit).
-template <class T>
-__device__ __forceinline__ T readlane_of(T x, int l) {
-  if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, readlane64(__builtin_bit_cast(uint64_t, x), l));
-  else return __builtin_bit_cast(T, readlane32(__builtin_bit_cast(uint32_t, x), l));
-}
 
 // Wave totals through LDS: this wave's exclusive prefix (wpre, wpref) and
 // the tile aggregate (agg, aggf), all folded left to right.  Contains one
@@ -752,11 +815,19 @@ __device__ __forceinline__ void static_done(const KernelArgs &a, uint32_t parity
 // whole wave; the result is uniform (>= tiles when none is left).  The
 // launch's last increment hands the workspace over: every workgroup has read
 // the parity before its first increment.
-__device__ __forceinline__ int64_t acquire_tile(const KernelArgs &a, uint32_t parity, int lane) {
-  uint64_t tk = 0, clear_hi = 0;
+// The increment itself (lane 0; the other lanes get 0), so that its round
+// trip can overlap other work before acquire_finish reads the result.
+__device__ __forceinline__ uint64_t acquire_issue(const KernelArgs &a, uint32_t parity, int lane) {
+  return lane == 0 ? __hip_atomic_fetch_add(&a.hdr->counter[parity], 1ull, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT)
+                   : 0ull;
+}
+// Clean the tile's word of the other parity, hand over after the launch's
+// last increment; returns the tile number, wave-uniform.
+__device__ __forceinline__ int64_t acquire_finish(const KernelArgs &a, uint32_t parity, int lane, uint64_t tk) {
+  uint64_t clear_hi = 0;
   uint32_t last = 0;
   if (lane == 0) {
-    tk = __hip_atomic_fetch_add(&a.hdr->counter[parity], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     last = tk == a.total_acquires - 1;
     if (tk < (uint64_t)a.tiles) st_agent(a.status + (1 - parity) * a.capacity + tk, 0ull);
     if (last) clear_hi = ld_agent(&a.hdr->dirty[1 - parity]);
@@ -764,6 +835,9 @@ __device__ __forceinline__ int64_t acquire_tile(const KernelArgs &a, uint32_t pa
   tk = readlane64(tk, 0);
   if (readlane32(last, 0)) hand_over(a, parity, readlane64(clear_hi, 0), 64);
   return (int64_t)tk;
+}
+__device__ __forceinline__ int64_t acquire_tile(const KernelArgs &a, uint32_t parity, int lane) {
+  return acquire_finish(a, parity, lane, acquire_issue(a, parity, lane));
 }
 
 // One tile per workgroup iteration.  Tile numbers come from the device counter
@@ -780,10 +854,16 @@ __device__ __forceinline__ int64_t acquire_tile(const KernelArgs &a, uint32_t pa
 // iteration, so consecutive tiles need no barrier between them.
 // MINW: waves per SIMD the register allocation must allow (the number of
 // workgroups of 4 waves resident per CU).
-template <class Op, int BLOCK, int ITEMS, bool SEG, bool NT, bool REV, bool VEC, int MINW>
+// EARLY (flat scans): the tile's aggregate is formed and published before
+// the in-register scan, from the lane sums of the in-lane partials, and the
+// first look-back poll (64*K1 tiles) is issued right behind it, so that its
+// round trip overlaps the scan and successors see the aggregate sooner.
+template <class Op, int BLOCK, int ITEMS, bool SEG, bool NT, bool REV, bool VEC, int MINW, bool EARLY = false>
 __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
   using SH = Shape<BLOCK, ITEMS>;
   constexpr int K = 4;   // look-back window = 64*K tiles per poll
+  constexpr int K1 = 1;  // EARLY: first poll, issued before the scan
+  constexpr bool kEarly = EARLY && !SEG;
   using carry_t = typename Op::carry_t;
 
   __shared__ carry_t s_wtot[2][SH::WAVES];
@@ -843,29 +923,67 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
     int fh;
     carry_t wsum, wpre, agg;
     uint32_t wflag, wpref, aggf;
-    scan_wave<Op, SH, SEG, REV>(a.exclusive, a.key, wave, lane, (head_waves >> wave) & 1u, s_heads, R, fh,
-                                wsum, wflag);
-    combine_waves<Op, SH::WAVES>(wave, lane, wsum, wflag, s_wtot[slot], s_wflag[slot], wpre, wpref, agg, aggf);
-
-    // publish, look back, publish the prefix
     bool first_is_head = false;
     if constexpr (SEG) first_is_head = (head_waves & 1u) && (s_heads[0] & 1u);
     const bool need_carry = t > 0 && !first_is_head;
-    if (multi && wave == 0) {
-      uint64_t *st = a.status + parity * a.capacity;
-      publish_first<Op>(st, t, agg, aggf);
-      if (a.ordered && lane == 0 && t != a.tiles - 1)
-        (void)__hip_atomic_fetch_add(a.pubcnt + (parity * kPubSlots + (t % kPubSlots)) * kPubStride, 1ull,
-                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      carry_t carry = Op::czero();
-      if (need_carry) {
-        uint64_t w[K];
-        lb_window<Op, K>(st, (int32_t)t - 1, w);
-        carry = look_back<Op, K>(st, t, a.spin_limit, a.err, w);
-        if (!aggf && lane == 0)
-          st_agent(st + t, Op::pack(Op::canon(Op::cadd(carry, Op::canon(agg))), kPrefix));
+    if constexpr (kEarly) {
+      // lane partials of every chunk as it arrives, and the lane total
+      constexpr int p3 = REV ? 0 : 3;
+      carry_t lt = Op::czero();
+#pragma unroll
+      for (int c = 0; c < SH::CH; ++c) {
+        chunk_lane<Op, REV>(R[c], a.key);
+        lt = Op::cadd(lt, Op::widen(Op::lfrom(R[c][p3])));
       }
-      if (lane == 0) s_carry[slot] = carry;
+      combine_waves<Op, SH::WAVES>(wave, lane, wave_total<Op>(lt), 0u, s_wtot[slot], s_wflag[slot], wpre, wpref,
+                                   agg, aggf);
+      // publish the aggregate and issue the first poll
+      uint64_t w1[K1];
+      if (multi && wave == 0) {
+        uint64_t *st = a.status + parity * a.capacity;
+        publish_first<Op>(st, t, agg, aggf);
+        if (a.ordered && lane == 0 && t != a.tiles - 1)
+          (void)__hip_atomic_fetch_add(a.pubcnt + (parity * kPubSlots + (t % kPubSlots)) * kPubStride, 1ull,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (need_carry) lb_window<Op, K1>(st, (int32_t)t - 1, w1);
+      }
+      // the rest of the scan while the poll is in flight
+      const bool ex = a.exclusive != 0u;
+      wsum = Op::czero();
+#pragma unroll
+      for (int c = 0; c < SH::CH; ++c) chunk_wave<Op, REV>(R[c], wsum, ex, c == 0);
+      fh = SH::WSPAN;
+      if (multi && wave == 0) {
+        uint64_t *st = a.status + parity * a.capacity;
+        carry_t carry = Op::czero();
+        if (need_carry) {
+          carry = look_back<Op, K1, K>(st, t, a.spin_limit, a.err, w1);
+          if (lane == 0) st_agent(st + t, Op::pack(Op::canon(Op::cadd(carry, Op::canon(agg))), kPrefix));
+        }
+        if (lane == 0) s_carry[slot] = carry;
+      }
+    } else {
+      scan_wave<Op, SH, SEG, REV>(a.exclusive, a.key, wave, lane, (head_waves >> wave) & 1u, s_heads, R, fh,
+                                  wsum, wflag);
+      combine_waves<Op, SH::WAVES>(wave, lane, wsum, wflag, s_wtot[slot], s_wflag[slot], wpre, wpref, agg, aggf);
+
+      // publish, look back, publish the prefix
+      if (multi && wave == 0) {
+        uint64_t *st = a.status + parity * a.capacity;
+        publish_first<Op>(st, t, agg, aggf);
+        if (a.ordered && lane == 0 && t != a.tiles - 1)
+          (void)__hip_atomic_fetch_add(a.pubcnt + (parity * kPubSlots + (t % kPubSlots)) * kPubStride, 1ull,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        carry_t carry = Op::czero();
+        if (need_carry) {
+          uint64_t w[K];
+          lb_window<Op, K>(st, (int32_t)t - 1, w);
+          carry = look_back<Op, K, K>(st, t, a.spin_limit, a.err, w);
+          if (!aggf && lane == 0)
+            st_agent(st + t, Op::pack(Op::canon(Op::cadd(carry, Op::canon(agg))), kPrefix));
+        }
+        if (lane == 0) s_carry[slot] = carry;
+      }
     }
     __syncthreads();
     const carry_t carry = need_carry ? s_carry[slot] : Op::czero();

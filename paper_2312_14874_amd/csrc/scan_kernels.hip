@@ -4,6 +4,7 @@
 #include "scan_table.hpp"
 #include "two_pass.hpp"
 #include "compact.hpp"
+#include "stream_ceiling.hpp"
 
 namespace mi355scan {
 
@@ -14,43 +15,49 @@ namespace mi355scan {
 // the most at which the flat variants do not spill).  Workgroups of 768 and
 // 1024 threads need 3 and 4 waves per SIMD to fit at all; some of their
 // reverse and segmented variants spill a few registers on rare paths.
-#define MI355SCAN_FNS(B, I, NT, VEC, WUF, WFF, WUS, WFS)                                      \
-  {{{(const void *)&scan_tiles<OpsU32, B, I, false, (NT != 0), false, VEC, WUF>,               \
-     (const void *)&scan_tiles<OpsU32, B, I, false, (NT != 0), true, VEC, WUF>},               \
+#define MI355SCAN_FNS(B, I, NT, VEC, WUF, WFF, WUS, WFS, E)                                   \
+  {{{(const void *)&scan_tiles<OpsU32, B, I, false, (NT != 0), false, VEC, WUF, E>,            \
+     (const void *)&scan_tiles<OpsU32, B, I, false, (NT != 0), true, VEC, WUF, E>},            \
     {(const void *)&scan_tiles<OpsU32, B, I, true, (NT != 0), false, VEC, WUS>,                \
      (const void *)&scan_tiles<OpsU32, B, I, true, (NT != 0), true, VEC, WUS>}},               \
-   {{(const void *)&scan_tiles<OpsF32, B, I, false, (NT != 0), false, VEC, WFF>,               \
-     (const void *)&scan_tiles<OpsF32, B, I, false, (NT != 0), true, VEC, WFF>},               \
+   {{(const void *)&scan_tiles<OpsF32, B, I, false, (NT != 0), false, VEC, WFF, E>,            \
+     (const void *)&scan_tiles<OpsF32, B, I, false, (NT != 0), true, VEC, WFF, E>},            \
     {(const void *)&scan_tiles<OpsF32, B, I, true, (NT != 0), false, VEC, WFS>,                \
      (const void *)&scan_tiles<OpsF32, B, I, true, (NT != 0), true, VEC, WFS>}},               \
-   {{(const void *)&scan_tiles<OpsMaxU32, B, I, false, (NT != 0), false, VEC, WUF>,            \
-     (const void *)&scan_tiles<OpsMaxU32, B, I, false, (NT != 0), true, VEC, WUF>},            \
+   {{(const void *)&scan_tiles<OpsMaxU32, B, I, false, (NT != 0), false, VEC, WUF, E>,         \
+     (const void *)&scan_tiles<OpsMaxU32, B, I, false, (NT != 0), true, VEC, WUF, E>},         \
     {(const void *)&scan_tiles<OpsMaxU32, B, I, true, (NT != 0), false, VEC, WUS>,             \
      (const void *)&scan_tiles<OpsMaxU32, B, I, true, (NT != 0), true, VEC, WUS>}},            \
-   {{(const void *)&scan_tiles<OpsXorU32, B, I, false, (NT != 0), false, VEC, WUF>,            \
-     (const void *)&scan_tiles<OpsXorU32, B, I, false, (NT != 0), true, VEC, WUF>},            \
+   {{(const void *)&scan_tiles<OpsXorU32, B, I, false, (NT != 0), false, VEC, WUF, E>,         \
+     (const void *)&scan_tiles<OpsXorU32, B, I, false, (NT != 0), true, VEC, WUF, E>},         \
     {(const void *)&scan_tiles<OpsXorU32, B, I, true, (NT != 0), false, VEC, WUS>,             \
      (const void *)&scan_tiles<OpsXorU32, B, I, true, (NT != 0), true, VEC, WUS>}}}
 
 // {block, items, nontemporal, waves per SIMD: u32 flat, f32 flat, u32 segmented, f32 segmented}
-#define MI355SCAN_TILES(B, I, NT, WUF, WFF, WUS, WFS) \
-  {B, I, NT, MI355SCAN_FNS(B, I, NT, true, WUF, WFF, WUS, WFS)}
+#define MI355SCAN_TILES(B, I, NT, WUF, WFF, WUS, WFS, E) \
+  {B, I, NT, MI355SCAN_FNS(B, I, NT, true, WUF, WFF, WUS, WFS, E), \
+   (const void *)&stream_tiles<B, I, (NT != 0), WUF>}
 
 const KernelShape kShapes[] = {
-    MI355SCAN_TILES(256, 16, 1, 7, 6, 5, 5),      // 0
-    MI355SCAN_TILES(256, 32, 1, 6, 5, 5, 3),      // 1
-    MI355SCAN_TILES(256, 64, 1, 3, 3, 3, 3),      // 2
-    MI355SCAN_TILES(256, 96, 1, 3, 2, 2, 2),      // 3
-    MI355SCAN_TILES(256, 128, 1, 2, 2, 2, 2),     // 4
-    MI355SCAN_TILES(512, 64, 1, 4, 2, 2, 2),      // 5
-    MI355SCAN_TILES(512, 128, 1, 2, 2, 2, 2),     // 6
-    MI355SCAN_TILES(1024, 64, 1, 4, 4, 4, 4),     // 7
-    MI355SCAN_TILES(768, 128, 1, 3, 3, 3, 3),     // 8
+    MI355SCAN_TILES(256, 16, 1, 7, 6, 5, 5, false),      // 0
+    MI355SCAN_TILES(256, 32, 1, 6, 5, 5, 3, false),      // 1
+    MI355SCAN_TILES(256, 64, 1, 3, 3, 3, 3, false),      // 2
+    MI355SCAN_TILES(256, 96, 1, 3, 2, 2, 2, false),      // 3
+    MI355SCAN_TILES(256, 128, 1, 2, 2, 2, 2, false),     // 4
+    MI355SCAN_TILES(512, 64, 1, 4, 2, 2, 2, false),      // 5
+    MI355SCAN_TILES(512, 128, 1, 2, 2, 2, 2, false),     // 6
+    MI355SCAN_TILES(1024, 64, 1, 4, 4, 4, 4, false),     // 7
+    MI355SCAN_TILES(768, 128, 1, 3, 3, 3, 3, false),     // 8
+    // flat scans publish the tile aggregate before the in-register scan
+    // (EARLY); segmented entries as the shapes above
+    MI355SCAN_TILES(512, 128, 1, 2, 2, 2, 2, true),      // 9
+    MI355SCAN_TILES(256, 128, 1, 2, 2, 2, 2, true),      // 10
+    MI355SCAN_TILES(256, 64, 1, 3, 3, 3, 3, true),       // 11
 };
 const int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 // Inputs or outputs that are not 16-byte aligned: dword accesses.
-const KernelShape kUnalignedShape = {256, 32, 1, MI355SCAN_FNS(256, 32, 1, false, 4, 4, 3, 3)};
+const KernelShape kUnalignedShape = {256, 32, 1, MI355SCAN_FNS(256, 32, 1, false, 4, 4, 3, 3, false), nullptr};
 
 // {shape, mode, workgroups per CU, percent of CUs}: see TileMode and Config.
 const Config kConfigs[] = {
@@ -66,6 +73,8 @@ const Config kConfigs[] = {
     {2, 1, 1, 100}, {3, 1, 1, 100},                   // 23-24
     {6, 4, 1, 100}, {8, 4, 1, 100},                   // 25-26 static round robin, one per CU
     {8, 1, 1, 75}, {8, 1, 1, 88}, {6, 1, 1, 75},      // 27-29 one per CU on part of the CUs
+    {9, 1, 1, 100}, {10, 1, 1, 100}, {11, 1, 1, 100},   // 30-32 early publication, one per CU
+    {10, 1, 2, 100}, {11, 1, 2, 100},                    // 33-34 early publication, two per CU
 };
 const int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 

@@ -11,6 +11,9 @@ struct KernelShape {
   // [kind: 0 = 32-bit integer sum, 1 = float32 sum, 2 = integer max / min
   //  (keyed), 3 = integer xor][segmented][reverse]
   const void *fn[4][2][2];
+  // the streaming-ceiling kernel of this shape (stream_ceiling.hpp): the same
+  // tiles and accesses without the scan; null for the unaligned shape
+  const void *copy;
 };
 
 enum TileMode {

@@ -43,32 +43,38 @@ def _loguniform_offsets(rng, n, lo=1, hi=1 << 20):
 
 
 def time_config(cfg, bufs, dtype_code, flags, seg_offsets, reps, stream):
-    """Median kernel time (ms) of configuration cfg over rotating buffers."""
+    """Median kernel time (ms) of configuration cfg over rotating buffers, each
+    launch between its own pair of HIP events; the GPU is kept busy while the
+    host enqueues, so that no launch waits for the host between its events."""
     L = _lib.lib
     force_config(cfg)
+
+    def launch(i):
+        x, y = bufs[i % len(bufs)]
+        if seg_offsets is None:
+            s = L.scan_flat(x.data_ptr(), y.data_ptr(), x.numel(), dtype_code, flags, stream)
+        else:
+            s = L.scan_segmented_batch(x.data_ptr(), y.data_ptr(), seg_offsets.data_ptr(),
+                                       seg_offsets.numel() - 1, x.numel(), dtype_code, flags, stream)
+        _lib.check(s, "tuning launch")
+
     try:
-        ts = []
-        for i in range(reps + 1):
-            x, y = bufs[i % len(bufs)]
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            if seg_offsets is None:
-                s = L.scan_flat(x.data_ptr(), y.data_ptr(), x.numel(), dtype_code, flags, stream)
-            else:
-                s = L.scan_segmented_batch(x.data_ptr(), y.data_ptr(), seg_offsets.data_ptr(),
-                                           seg_offsets.numel() - 1, x.numel(), dtype_code, flags, stream)
-            _lib.check(s, "tuning launch")
-            e1.record()
-            torch.cuda.synchronize()
-            if i:
-                ts.append(e0.elapsed_time(e1))
-        ts.sort()
+        launch(0)                                   # warm-up (and workspace growth)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        torch.cuda._sleep(int(max(reps * 60e-6, 2e-3) * 2.4e9))
+        for i in range(reps):
+            ev[i][0].record()
+            launch(i + 1)
+            ev[i][1].record()
+        torch.cuda.synchronize()
+        ts = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
         return ts[len(ts) // 2]
     finally:
         force_config(-1)
 
 
-def sweep(n, dtype="int", segmented=False, reps=7, verbose=True, seed=0):
+def sweep(n, dtype="int", segmented=False, reps=11, verbose=True, seed=0):
     dev = torch.device("cuda", torch.cuda.current_device())
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     tdt = torch.float32 if dtype == "f32" else torch.int32
@@ -92,7 +98,25 @@ def sweep(n, dtype="int", segmented=False, reps=7, verbose=True, seed=0):
             print("  n=2^%-2d %-3s seg=%d cfg %2d (block %4d items %2d nt %d mode %d): %9.2f us  %7.1f GB/s"
                   % (int(np.log2(n)), dtype, segmented, cfg, info["block"], info["items"], info["nontemporal"],
                      info["mode"], ms * 1e3, 8 * n / (ms * 1e-3) / 1e9), file=sys.stderr, flush=True)
-    return min(res)[1], res
+    return pick(res), res
+
+
+# A configuration whose tile order relies on the dispatcher (mode 2: tile =
+# workgroup index, in-order dispatch assumed) or on co-residency (mode 4) is
+# taken only when it beats the best counter-mode configuration by more than
+# this fraction (the library's scan_autotune applies the same rule).
+ORDERED_MARGIN = 0.03
+
+
+def pick(res):
+    """The fastest configuration of res [(ms, cfg)], preferring counter modes
+    (0, 1) unless another mode wins by more than ORDERED_MARGIN."""
+    best_ms, best = min(res)
+    dyn = [(ms, c) for ms, c in res if config_info(c)["mode"] in (0, 1)]
+    if not dyn:
+        return best
+    dyn_ms, dyn_best = min(dyn)
+    return best if best_ms < dyn_ms * (1.0 - ORDERED_MARGIN) else dyn_best
 
 
 def main():
@@ -100,7 +124,7 @@ def main():
     p.add_argument("--out", default=DEFAULT_OUT)
     p.add_argument("--min", type=int, default=10)
     p.add_argument("--max", type=int, default=30)
-    p.add_argument("--reps", type=int, default=7)
+    p.add_argument("--reps", type=int, default=11)
     p.add_argument("--dtypes", default="int,f32")
     p.add_argument("--segmented", default="0,1")
     p.add_argument("--merge", action="store_true",

@@ -234,3 +234,17 @@ def test_tune_file_roundtrip(tmp_path):
         p.write_text('{"entries": []}')
         tune_load(str(p))
     assert lib.scan_tune_load(str(tmp_path / "missing.json").encode()) == INVALID
+
+
+@pytest.mark.parametrize("args,code", [
+    ((4096, 1 << 20, 10, -1), INVALID),       # unknown configuration
+    ((4096, 1 << 20, 10, 10 ** 6), INVALID),
+    ((4100, 1 << 20, 10, 22), INVALID),       # not 16-byte aligned
+    ((4096, 4100, 10, 22), OVERLAP),          # partial overlap
+    ((4096, 1 << 20, 10, 0), 5),              # tile = workgroup index: not a counter mode
+    ((4096, 1 << 20, 10, 8), 5),              # static round robin: not a counter mode
+    ((None, None, 0, 22), 0),                 # n = 0
+])
+def test_stream_ceiling_argument_errors(args, code):
+    L = _lib()
+    assert L.lib.scan_stream_ceiling(*args, None) == code
