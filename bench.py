@@ -44,6 +44,24 @@ resident in HBM.  Prints ONE JSON line on stdout; progress goes to stderr.
              normal(0,1), inclusive, kernel time from HIP events at 16 bytes
              per element; uint64 checked exactly by its recurrence on the GPU,
              float64 against the oracle within its bound in the CPU legs
+  ceiling    the streaming-ceiling kernel (out = in + 1 with the scan's tiles,
+             accesses, resident grid and store/load hand-off, but no scan and
+             no look-back) over every counter-mode configuration on the same
+             input; frac_copy = the scan's GB/s over the best of them, and over
+             the one of the scan's own configuration; each result checked
+             exactly (y = x + 1) on the GPU
+  sizes      the other sizes of the workloads: 2^20 int32 in [0, 100)
+             inclusive and exclusive (64 rotating buffer pairs), the uint32
+             bandwidth curve at 2^24 (8 rotating pairs), 2^28 in place and 2^30;
+             kernel time per launch from HIP events (median, p10, p90), each
+             result checked exactly on the GPU by its recurrence
+  float32    inclusive scan of 2^28 float32 normal(0,1) (seed 1003), checked
+             against the oracle within 2^-20 * sum|a| in the CPU legs
+  autograd   the differentiable cumsum on 64 ragged rows (lengths log-uniform
+             in [2^10, 2^22], seed 1005): forward (segmented inclusive scan) and
+             backward (segmented reverse scan) kernel times, and one
+             forward + backward through torch.autograd; both results checked
+             against the oracle in the CPU legs
 Extra modes (not the headline line): --n, --dtype f32, --copy-calibration.
 """
 from __future__ import annotations
@@ -106,6 +124,10 @@ def parse():
     p.add_argument("--no-operators", action="store_true", help="skip the max / min / xor scans")
     p.add_argument("--no-compaction", action="store_true", help="skip the stream compaction")
     p.add_argument("--no-wide", action="store_true", help="skip the 64-bit scans")
+    p.add_argument("--no-ceiling", action="store_true", help="skip the streaming-ceiling sweep")
+    p.add_argument("--no-sizes", action="store_true", help="skip the other sizes (2^20, 2^24, in place, 2^30)")
+    p.add_argument("--no-float32", action="store_true", help="skip the float32 scan at 2^28")
+    p.add_argument("--no-autograd", action="store_true", help="skip the autograd rows")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run only plain device copies of the scan's bytes (counter calibration)")
     return p.parse_args()
@@ -203,6 +225,12 @@ def main():
         parity = "unchecked (--no-cpu)"
     log("parity:", parity)
 
+    # ---------------------------------------------------------- streaming ceiling of the access pattern
+    ceil = None
+    scan_cfg = scan.selected_config(torch.int32 if args.dtype == "u32" else torch.float32, n)
+    if not args.no_ceiling and args.dtype == "u32":
+        ceil = ceiling_runs(scan, torch, x, y, stream, scan_cfg, achieved)
+
     # ---------------------------------------------------------- segmented vs per-launch
     seg = None
     if not args.no_segmented and args.dtype == "u32":
@@ -223,7 +251,19 @@ def main():
     if not args.no_compaction and args.dtype == "u32":
         comp = compaction_run(scan, torch, x, y, stream)
 
+    # ---------------------------------------------------------- the other sizes (in place at n)
+    sizes = None
+    if not args.no_sizes and args.dtype == "u32":
+        sizes = size_runs(scan, torch, np, workloads, x, y, stream)
+
     del x, y
+    # ---------------------------------------------------------- float32 and autograd (checked in the CPU legs)
+    f32, f32_data, ag, ag_data = None, None, None, None
+    if not args.no_float32 and args.dtype == "u32":
+        f32, f32_data = float32_run(scan, torch, workloads, stream)
+    if not args.no_autograd and args.dtype == "u32":
+        ag, ag_data = autograd_run(scan, torch, workloads, stream)
+
     # ---------------------------------------------------------- 64-bit elements
     wide, wide_f64 = None, None
     if not args.no_wide and args.dtype == "u32":
@@ -233,11 +273,16 @@ def main():
     cpu, cpu_ctx = None, None
     if not args.no_cpu:
         cpu, cpu_ctx, f64_ok = cpu_legs(args, np, a, got, alg_bytes, wide_f64)
+        cpu.update(host_info())
         if args.dtype == "f32":
             parity = "within 2^-20*sum|a|" if cpu["gpu_result_within_bound"] else "MISMATCH"
         if wide is not None:
             wide["f64_vs_oracle"] = f64_ok
-    del wide_f64
+        if f32 is not None:
+            f32["within_bound_vs_oracle"] = float32_check(np, *f32_data)
+        if ag is not None:
+            ag.update(autograd_check(np, *ag_data))
+    del wide_f64, f32_data, ag_data
 
     traffic = measured_traffic(n) if args.dtype == "u32" else None
     out = {
@@ -256,13 +301,20 @@ def main():
         "config": {"workload": "inclusive scan, n=2^%d %s (%s), out of place, single pass"
                                % (n.bit_length() - 1, "uint32 full-range, wrapping" if args.dtype == "u32"
                                   else "float32 normal(0,1)", "seed %d" % (1002 if args.dtype == "u32" else 1003)),
-                   "n": n, "scan_config": scan.selected_config(torch.int32 if args.dtype == "u32" else torch.float32, n),
+                   "n": n, "scan_config": scan_cfg,
                    "parity": parity},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_GBS, 4), "traffic": traffic,
-                     "kernel_avg_us": round(kern_avg_ms * 1e3, 2), "algorithmic_bytes": int(alg_bytes)},
+                     "kernel_avg_us": round(kern_avg_ms * 1e3, 2), "algorithmic_bytes": int(alg_bytes),
+                     "Gelem_per_s": round(n / (kern_avg_ms * 1e-3) / 1e9, 2),
+                     "frac_copy": ceil["frac_copy"] if ceil else None,
+                     "frac_copy_same_config": ceil["frac_copy_same_config"] if ceil else None},
         "cpu_baseline": cpu,
         "cpu_context": cpu_ctx,
+        "ceiling": ceil,
+        "sizes": sizes,
+        "float32": f32,
+        "autograd": ag,
         "segmented": seg,
         "two_pass": two,
         "operators": ops,
@@ -270,6 +322,215 @@ def main():
         "wide": wide,
     }
     print(json.dumps(out), flush=True)
+
+
+def host_info():
+    """The host the CPU legs ran on: CPU model and core counts."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"host_cpu": model, "host_nproc": os.cpu_count(), "host_cpus_usable": len(os.sched_getaffinity(0))}
+
+
+def ceiling_runs(scan, torch, x, y, stream, scan_cfg, scan_GBps):
+    """The streaming-ceiling kernel (the scan's memory access pattern without
+    the scan) on the bench input, over every counter-mode configuration; each
+    result is checked exactly (y = x + 1 modulo 2^32)."""
+    import ctypes
+    n = x.numel()
+    sptr = ctypes.c_void_p(stream.cuda_stream)
+    runs, exact = [], True
+    for c in range(scan.num_configs()):
+        info = scan.config_info(c)
+        if info["mode"] not in (0, 1):
+            continue
+
+        def run():
+            scan.check(scan.lib.scan_stream_ceiling(x.data_ptr(), y.data_ptr(), n, c, sptr), "scan_stream_ceiling")
+        run()
+        torch.cuda.synchronize()
+        exact = exact and bool(torch.equal(y, x + 1))
+        ms = _median_ms(torch, run, stream, 10)
+        runs.append({"config": c, "block": info["block"], "items": info["items"], "per_cu": info["per_cu"],
+                     "cu_pct": info["cu_pct"], "us": round(ms * 1e3, 1),
+                     "GBps": round(8.0 * n / (ms * 1e-3) / 1e9, 1)})
+    best = max(runs, key=lambda r: r["GBps"])
+    same = next((r for r in runs if r["config"] == scan_cfg), None)
+    res = {"workload": "out = in + 1 over the same n=2^%d input with the scan's tiles, accesses, grid and "
+                       "store/load hand-off, no scan and no look-back" % (n.bit_length() - 1),
+           "best_config": best["config"], "best_us": best["us"], "best_GBps": best["GBps"],
+           "frac_copy": round(scan_GBps / best["GBps"], 4),
+           "same_config": scan_cfg, "same_config_us": same["us"] if same else None,
+           "same_config_GBps": same["GBps"] if same else None,
+           "frac_copy_same_config": round(scan_GBps / same["GBps"], 4) if same else None,
+           "runs": runs, "results_exact": exact}
+    log("ceiling: best config %d %.1f GB/s, scan's config %s %s GB/s" % (
+        best["config"], best["GBps"], scan_cfg, same["GBps"] if same else None))
+    return res
+
+
+def _per_launch_ms(torch, fns, stream, reps):
+    """Kernel time of each launch from its own pair of HIP events on the
+    stream; launch i runs fns[i % len(fns)] (rotating buffers)."""
+    for f in fns:
+        f()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    # keep the GPU busy while the host enqueues, so that no launch waits for
+    # the host between its two events (a few tens of microseconds per call)
+    torch.cuda._sleep(int(max(reps * 60e-6, 5e-3) * 2.4e9))
+    for i in range(reps):
+        ev[i][0].record(stream)
+        fns[i % len(fns)]()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    ts = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    return ts[len(ts) // 2], ts[reps // 10], ts[(9 * reps) // 10]
+
+
+def size_runs(scan, torch, np, workloads, x, y, stream):
+    """2^20 int32 in [0, 100) inclusive and exclusive; uint32 full-range at
+    2^24, 2^28 in place (on the bench input) and 2^30.  Inputs below 2^25
+    elements rotate over enough buffer pairs (>= 512 MiB) that the 256 MB
+    last-level cache cannot serve repeated launches.  Each result is checked
+    exactly on the GPU: inclusive y[0] = x[0], y[i] - y[i-1] = x[i];
+    exclusive y[0] = 0, y[i] - y[i-1] = x[i-1] (modulo 2^32)."""
+    dev = x.device
+    rows = []
+
+    def row(name, n, t, exact, nbuf):
+        ms, p10, p90 = t
+        r = {"case": name, "n": n, "us": round(ms * 1e3, 2), "p10_us": round(p10 * 1e3, 2),
+             "p90_us": round(p90 * 1e3, 2), "GBps": round(8.0 * n / (ms * 1e-3) / 1e9, 1),
+             "Gelem_per_s": round(n / (ms * 1e-3) / 1e9, 2), "buffer_pairs": nbuf, "exact": bool(exact)}
+        rows.append(r)
+        log("sizes:", r)
+
+    def exclusive_holds(xx, yy):
+        return bool(yy[0] == 0) and bool(torch.equal(yy[1:] - yy[:-1], xx[:-1]))
+
+    # 2^20 int32 in [0, 100): inclusive and exclusive, 64 buffer pairs (512 MiB)
+    n1 = 1 << 20
+    src = torch.from_numpy(workloads.uniform_i32(n1)).to(dev)
+    pairs = [(src.clone(), torch.empty_like(src)) for _ in range(64)]
+    for ex in (False, True):
+        fns = [lambda p=p: scan.cumsum(p[0], exclusive=ex, out=p[1]) for p in pairs]
+        t = _per_launch_ms(torch, fns, stream, 200)
+        xx, yy = pairs[0]
+        ok = exclusive_holds(xx, yy) if ex else inclusive_sum_holds(torch, xx, yy)
+        row("int32 uniform[0,100) %s, n=2^20" % ("exclusive" if ex else "inclusive"), n1, t, ok, len(pairs))
+    del pairs, src
+    # 2^24 uint32: 8 buffer pairs (1 GiB)
+    n2 = 1 << 24
+    src = torch.from_numpy(workloads.full_u32(n2).view(np.int32)).to(dev)
+    pairs = [(src.clone(), torch.empty_like(src)) for _ in range(8)]
+    fns = [lambda p=p: scan.cumsum(p[0], out=p[1]) for p in pairs]
+    t = _per_launch_ms(torch, fns, stream, 100)
+    row("uint32 full-range inclusive, n=2^24", n2, t, inclusive_sum_holds(torch, *pairs[0]), len(pairs))
+    del pairs, src
+    # 2^28 in place on a copy of the bench input
+    z = x.clone()
+    scan.cumsum(z, out=z)
+    torch.cuda.synchronize()
+    ok = inclusive_sum_holds(torch, x, z)
+    t = _per_launch_ms(torch, [lambda: scan.cumsum(z, out=z)], stream, 50)
+    row("uint32 full-range inclusive in place, n=2^28", x.numel(), t, ok, 1)
+    del z
+    # 2^30 uint32
+    n3 = 1 << 30
+    big = torch.from_numpy(workloads.full_u32(n3).view(np.int32)).to(dev)
+    out = torch.empty_like(big)
+    t = _per_launch_ms(torch, [lambda: scan.cumsum(big, out=out)], stream, 20)
+    row("uint32 full-range inclusive, n=2^30", n3, t, inclusive_sum_holds(torch, big, out), 1)
+    del big, out
+    return {"workload": "other sizes: int32 [0,100) seed 1001, uint32 full-range seed 1002; out of place unless "
+                        "stated", "runs": rows}
+
+
+def float32_run(scan, torch, workloads, stream):
+    """Inclusive scan of 2^28 float32 normal(0,1); the input and result go to
+    the CPU legs for the comparison with the oracle."""
+    n = 1 << 28
+    a = workloads.normal_f32(n)
+    x = torch.from_numpy(a).to("cuda")
+    y = torch.empty_like(x)
+    ms, p10, p90 = _per_launch_ms(torch, [lambda: scan.cumsum(x, out=y)], stream, 50)
+    res = {"workload": "inclusive scan, n=2^28 float32 normal(0,1) (seed 1003)",
+           "scan_config": scan.selected_config(torch.float32, n), "us": round(ms * 1e3, 1),
+           "p10_us": round(p10 * 1e3, 1), "p90_us": round(p90 * 1e3, 1),
+           "GBps": round(8.0 * n / (ms * 1e-3) / 1e9, 1), "Gelem_per_s": round(n / (ms * 1e-3) / 1e9, 2)}
+    log("float32:", res)
+    got = y.cpu().numpy()
+    del x, y
+    return res, (a, got)
+
+
+def float32_check(np, a, got):
+    import oracle
+    ref, ab = oracle.scan_f32(a)
+    return bool(np.all(np.abs(got.astype(np.float64) - ref) <= oracle.f32_tolerance(ab)))
+
+
+def autograd_run(scan, torch, workloads, stream):
+    """The differentiable cumsum on 64 ragged rows: kernel times of the
+    forward (segmented inclusive scan) and the backward (segmented reverse
+    scan), and the time of one forward + backward through torch.autograd."""
+    xs, gs, off = workloads.rows()
+    n = xs.size
+    x = torch.from_numpy(xs).to("cuda")
+    g = torch.from_numpy(gs).to("cuda")
+    offs = torch.from_numpy(off).to("cuda")
+    y = torch.empty_like(x)
+    gx = torch.empty_like(x)
+    fwd = _per_launch_ms(torch, [lambda: scan.segmented_scan(x, offs, out=y)], stream, 50)
+    bwd = _per_launch_ms(torch, [lambda: scan.cumsum_backward(g, offs, out=gx)], stream, 50)
+    xr = x.clone().requires_grad_(True)
+
+    def both():
+        yy = scan.cumsum_autograd(xr, offs)
+        yy.backward(g)
+        return yy
+    both()
+    torch.cuda.synchronize()
+    w = []
+    for _ in range(10):
+        xr.grad = None
+        w0 = time.perf_counter()
+        yy = both()
+        torch.cuda.synchronize()
+        w.append(time.perf_counter() - w0)
+    w.sort()
+    res = {"workload": "64 rows, lengths log-uniform in [2^10, 2^22] (n=%d), x and upstream grad normal(0,1) "
+                       "(seed 1005)" % n,
+           "forward_us": round(fwd[0] * 1e3, 1), "backward_us": round(bwd[0] * 1e3, 1),
+           "forward_GBps": round(8.0 * n / (fwd[0] * 1e-3) / 1e9, 1),
+           "backward_GBps": round(8.0 * n / (bwd[0] * 1e-3) / 1e9, 1),
+           "autograd_fwd_bwd_wall_us": round(w[len(w) // 2] * 1e6, 1)}
+    log("autograd:", res)
+    data = (xs, gs, off, yy.detach().cpu().numpy(), xr.grad.cpu().numpy(), y.cpu().numpy(), gx.cpu().numpy())
+    del x, g, offs, y, gx, xr
+    return res, data
+
+
+def autograd_check(np, xs, gs, off, y_ag, gx_ag, y_k, gx_k):
+    """Forward and backward of the autograd rows against the oracle's
+    per-row scan and suffix sums, within 2^-20 times the running sum of |.|."""
+    import oracle
+    ref, ab = oracle.segmented_f32(xs, off)
+    tol = oracle.f32_tolerance(ab)
+    fwd_ok = bool(np.all(np.abs(y_ag.astype(np.float64) - ref) <= tol)) and \
+        bool(np.all(np.abs(y_k.astype(np.float64) - ref) <= tol))
+    ref, ab = oracle.segmented_f32(gs, off, reverse=True)
+    tol = oracle.f32_tolerance(ab)
+    bwd_ok = bool(np.all(np.abs(gx_ag.astype(np.float64) - ref) <= tol)) and \
+        bool(np.all(np.abs(gx_k.astype(np.float64) - ref) <= tol))
+    return {"forward_within_bound_vs_oracle": fwd_ok, "backward_within_bound_vs_oracle": bwd_ok}
 
 
 def compaction_run(scan, torch, x, y, stream):
