@@ -128,6 +128,9 @@ def parse():
     p.add_argument("--no-sizes", action="store_true", help="skip the other sizes (2^20, 2^24, in place, 2^30)")
     p.add_argument("--no-float32", action="store_true", help="skip the float32 scan at 2^28")
     p.add_argument("--no-autograd", action="store_true", help="skip the autograd rows")
+    p.add_argument("--no-graphs", action="store_true",
+                   help="segmented leg: eager launches only (no graph replays; rocprofv3's counter mode "
+                        "does not survive graph launches)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run only plain device copies of the scan's bytes (counter calibration)")
     return p.parse_args()
@@ -234,7 +237,7 @@ def main():
     # ---------------------------------------------------------- segmented vs per-launch
     seg = None
     if not args.no_segmented and args.dtype == "u32":
-        seg = segmented_comparison(scan, torch, np, workloads, dev)
+        seg = segmented_comparison(scan, torch, np, workloads, dev, graphs=not args.no_graphs)
 
     # ---------------------------------------------------------- two-pass algorithms vs the single pass
     two = None
@@ -541,26 +544,12 @@ def compaction_run(scan, torch, x, y, stream):
     def run():
         scan.compact_into(x, y, cnt, "greater", 0)
 
-    def timed(fn, reps):
-        fn()
-        torch.cuda.synchronize()
-        ts = []
-        for _ in range(reps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            fn()
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1))
-        ts.sort()
-        return ts[len(ts) // 2]
-
-    ms = timed(run, 20)
+    ms = _median_ms(torch, run, stream, 20)
     k = int(cnt.item())
     want = torch.masked_select(x, x > 0)
     ok = k == want.numel() and bool(torch.equal(y[:k], want))
     del want
-    ms_torch = timed(lambda: torch.masked_select(x, x > 0), 5)
+    ms_torch = _sync_median_ms(torch, lambda: torch.masked_select(x, x > 0), stream, 5)
     moved = 4.0 * n + 4.0 * k
     res = {"workload": "keep x > 0 of the same n=2^%d input read as int32 (%d kept)" % (n.bit_length() - 1, k),
            "fused_us": round(ms * 1e3, 1), "GBps_moved": round(moved / (ms * 1e-3) / 1e9, 1),
@@ -568,7 +557,7 @@ def compaction_run(scan, torch, x, y, stream):
            "speedup_vs_torch": round(ms_torch / ms, 2), "results_equal_torch_masked_select": bool(ok)}
     # two-way partition: every element written once (8 bytes per element)
     z = torch.empty_like(x)
-    ms_p = timed(lambda: scan.partition_into(x, z, cnt, "greater", 0), 20)
+    ms_p = _median_ms(torch, lambda: scan.partition_into(x, z, cnt, "greater", 0), stream, 20)
     kp = int(cnt.item())
     keep = x > 0
     ok_p = kp == k and bool(torch.equal(z[:kp], torch.masked_select(x, keep))) and \
@@ -645,6 +634,16 @@ def cpu_legs(args, np, a, got, alg_bytes, wide_f64):
 
 
 def _median_ms(torch, fn, stream, reps):
+    """Median kernel time of fn (which must not synchronise the host): each
+    launch between its own pair of HIP events, all enqueued behind a GPU-side
+    sleep so that no launch waits for the host between its events."""
+    return _per_launch_ms(torch, [fn], stream, reps)[0]
+
+
+def _sync_median_ms(torch, fn, stream, reps):
+    """Median time of fn between HIP events with the host synchronised before
+    every call: for calls that synchronise by themselves or are bound by
+    host-side launches (their host cost belongs to the measurement)."""
     fn()
     torch.cuda.synchronize()
     ts = []
@@ -729,16 +728,7 @@ def two_pass_comparison(scan, torch, x, y, single_ms, stream):
             run()
             torch.cuda.synchronize()
             equal = equal and bool(torch.equal(z, y))
-            ts = []
-            for _ in range(10):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                run()
-                e1.record(stream)
-                torch.cuda.synchronize()
-                ts.append(e0.elapsed_time(e1))
-            ts.sort()
-            ms = ts[len(ts) // 2]
+            ms = _median_ms(torch, run, stream, 10)
             rows.append({"method": method, "partition": part, "us": round(ms * 1e3, 1),
                          "GBps_alg": round(8.0 * n / (ms * 1e-3) / 1e9, 1),
                          "min_bytes_per_elem": floor,
@@ -749,8 +739,9 @@ def two_pass_comparison(scan, torch, x, y, single_ms, stream):
             "single_pass_us": round(single_ms * 1e3, 1), "runs": rows, "results_equal": equal}
 
 
-def segmented_comparison(scan, torch, np, workloads, dev):
-    """Batched segmented scan (graph replay) vs one launch per segment."""
+def segmented_comparison(scan, torch, np, workloads, dev, graphs=True):
+    """Batched segmented scan (graph replay) vs one launch per segment; with
+    graphs=False only the eager launches (the graph fields are null)."""
     import ctypes
     t0 = time.time()
     vals, off = workloads.segments()
@@ -765,28 +756,18 @@ def segmented_comparison(scan, torch, np, workloads, dev):
     stream = torch.cuda.current_stream(dev)
     sptr = ctypes.c_void_p(stream.cuda_stream)
 
-    def timed(fn, reps):
-        fn()
-        torch.cuda.synchronize()
-        ts = []
-        for _ in range(reps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            fn()
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1))
-        ts.sort()
-        return ts[len(ts) // 2]
-
-    g_batched = scan.SegmentedScanGraph(x, y_b, offs, exclusive=True)
-    t_batched = timed(g_batched.launch, 20)
-    t_batched_eager = timed(lambda: scan.segmented_scan(x, offs, exclusive=True, out=y_b), 20)
-    t_looped = timed(lambda: scan.check(scan.lib.scan_segmented_looped(
-        x.data_ptr(), y_l.data_ptr(), off.ctypes.data, S, scan.SCAN_I32, scan.SCAN_EXCLUSIVE, sptr)), 5)
-    g_looped = scan.LoopedScanGraph(x, y_g, off, exclusive=True)
-    t_looped_graph = timed(g_looped.launch, 5)
-    g_batched.launch()
+    g_batched = scan.SegmentedScanGraph(x, y_b, offs, exclusive=True) if graphs else None
+    t_batched = _median_ms(torch, g_batched.launch, stream, 20) if graphs else None
+    t_batched_eager = _median_ms(torch, lambda: scan.segmented_scan(x, offs, exclusive=True, out=y_b), stream, 20)
+    # one launch per segment is bound by the host's launches: timed with them
+    t_looped = _sync_median_ms(torch, lambda: scan.check(scan.lib.scan_segmented_looped(
+        x.data_ptr(), y_l.data_ptr(), off.ctypes.data, S, scan.SCAN_I32, scan.SCAN_EXCLUSIVE, sptr)), stream, 5)
+    g_looped = scan.LoopedScanGraph(x, y_g, off, exclusive=True) if graphs else None
+    t_looped_graph = _median_ms(torch, g_looped.launch, stream, 5) if graphs else None
+    if graphs:
+        g_batched.launch()
+    else:
+        scan.segmented_scan(x, offs, exclusive=True, out=y_b)
     torch.cuda.synchronize()
     # an exclusive segmented +-scan is characterised exactly by y = 0 at every
     # segment start and y[i] = y[i-1] + x[i-1] elsewhere (mod 2^32)
@@ -795,20 +776,22 @@ def segmented_comparison(scan, torch, np, workloads, dev):
     start[first[first < n]] = True
     ok_b = bool((y_b[start] == 0).all()) and bool(((y_b[1:] - y_b[:-1] - x[:-1])[~start[1:]] == 0).all())
     ok_l = bool(torch.equal(y_l, y_b))
-    ok_g = bool(torch.equal(y_g, y_b))
+    ok_g = bool(torch.equal(y_g, y_b)) if graphs else True   # no graph result without graphs
     del start
-    g_batched.close()
-    g_looped.close()
+    if graphs:
+        g_batched.close()
+        g_looped.close()
     alg = 8.0 * n + 8.0 * (S + 1)
+    t_b = t_batched if graphs else t_batched_eager
     res = {
         "workload": "exclusive per-segment scan, S=%d, n=%d int32 Poisson(8), lengths log-uniform [1,2^20] (seed 1004)" % (S, n),
-        "batched_graph_us": round(t_batched * 1e3, 1),
+        "batched_graph_us": round(t_batched * 1e3, 1) if graphs else None,
         "batched_eager_us": round(t_batched_eager * 1e3, 1),
         "per_launch_eager_us": round(t_looped * 1e3, 1),
-        "per_launch_graph_us": round(t_looped_graph * 1e3, 1),
-        "speedup_vs_eager": round(t_looped / t_batched, 2),
-        "speedup_vs_graph": round(t_looped_graph / t_batched, 2),
-        "batched_GBps": round(alg / (t_batched * 1e-3) / 1e9, 1),
+        "per_launch_graph_us": round(t_looped_graph * 1e3, 1) if graphs else None,
+        "speedup_vs_eager": round(t_looped / t_b, 2),
+        "speedup_vs_graph": round(t_looped_graph / t_b, 2) if graphs else None,
+        "batched_GBps": round(alg / (t_b * 1e-3) / 1e9, 1),
         "results_equal": bool(ok_b and ok_l and ok_g),
     }
     log("segmented:", res)

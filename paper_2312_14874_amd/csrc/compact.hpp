@@ -29,14 +29,23 @@ __device__ __forceinline__ bool keep_element(uint32_t x, const CompactArgs &a) {
 // selection mask (8 chunks per register); the tile total needs only the
 // lanes' counts, and a chunk's positions are scanned when it is written.
 // The values stay in R until they are written: per chunk, the wave packs its
-// kept elements into its own LDS row and writes them out as one contiguous
-// run (dword stores of consecutive lanes) instead of one scattered store per
-// element; as in scan_tiles, the registers a packed chunk frees take the next
-// tile's chunk at once.
+// kept elements into its own LDS row (every element is written somewhere, so
+// no per-element branch) and writes them out as one contiguous run, one
+// 128-bit store per lane, instead of one scattered store per element; as in
+// scan_tiles, the registers a packed chunk frees take the next tile's chunk at
+// once.  The output offsets are wave-uniform and kept in scalar registers:
+// a buffer resource the compiler must treat as per-lane would turn every
+// store into a loop over its distinct values.
+// Counts of kept elements: 32-bit integer sums whose wave totals are folded
+// from one lane each (no register per wave's total).
+struct OpsCount : OpsU32 {
+  static constexpr bool kCombineByLane = true;
+};
+
 template <int BLOCK, int ITEMS, bool VEC, int MINW, bool PART = false>
 __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
   using SH = Shape<BLOCK, ITEMS>;
-  using Op = OpsU32;
+  using Op = OpsCount;
   constexpr int K = 4;
   // store cache policy: non-temporal for compaction; the partition's two
   // output streams write faster through the default policy (measured)
@@ -47,7 +56,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
   __shared__ uint32_t s_carry;
   __shared__ int64_t s_tile;
   __shared__ uint32_t s_parity;
-  __shared__ uint32_t s_stage[SH::WAVES][256];
+  __shared__ __attribute__((aligned(16))) uint32_t s_stage[SH::WAVES][768];   // see pack
   const KernelArgs &ka = a.k;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -93,6 +102,9 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
       for (int k = 0; k < 4; ++k) m |= (c * 256 + k < rem && keep_element(R[c][k], a)) ? (1u << k) : 0u;
       mask[c / 8] |= m << (4 * (c % 8));
       lane_kept += (uint32_t)__builtin_popcount(m);
+      // finish the chunk's bits now: left to itself the compiler keeps every
+      // element's bit in a register of its own until the end of the pass
+      asm volatile("" : "+v"(mask[c / 8]), "+v"(lane_kept));
     }
     const uint32_t wsum = readlane32(wave_scan<Op>(lane_kept), 63);
     uint32_t wpre, agg, wpref, aggf;
@@ -110,18 +122,18 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
       if (lane == 0) s_carry = carry;
     }
     __syncthreads();
-    const uint32_t carry = t > 0 ? s_carry : 0u;
+    // carry and base are wave-uniform; saying so keeps the output buffer
+    // resources in scalar registers (a resource the compiler must treat as
+    // per-lane turns every store into a loop over its distinct values)
+    const uint32_t carry = (uint32_t)__builtin_amdgcn_readfirstlane((int)(t > 0 ? s_carry : 0u));
     if (t == ka.tiles - 1 && tid == 0) *a.count = (int64_t)(carry + agg);
     // kept elements go to out[carry + wpre + (kept in the wave's earlier
     // chunks) + (kept in earlier lanes of the chunk) + (kept before k in the group)]
-    const uint32_t base = carry + wpre;
+    const uint32_t base = (uint32_t)__builtin_amdgcn_readfirstlane((int)(carry + wpre));
     // the kept elements' range out[base, n), clamped to [0, 2^31) bytes: a
     // start beyond n (only after a look-back that gave up) writes nothing
     const int64_t kbytes = (ka.n - (int64_t)base) * 4;
     const bool kok = kbytes > 0;
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        static_cast<uint32_t *>(ka.out) + (kok ? base : 0u), (short)0,
-        kok ? (int)(kbytes > 0x7fffffff ? 0x7fffffff : kbytes) : 0, 0x00020000);
     uint32_t *stage = s_stage[wave];
     uint32_t cb = 0u;   // kept in the wave's chunks so far (uniform)
     // partition: the wave's rejected elements go to out[rlo, rlo + rej) in
@@ -129,57 +141,72 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
     // a range outside [0, n) (only after a look-back that gave up) writes nothing
     const int64_t wvalid64 = ka.n - wb;
     const uint32_t wvalid = wvalid64 <= 0 ? 0u : (wvalid64 >= SH::WSPAN ? (uint32_t)SH::WSPAN : (uint32_t)wvalid64);
-    __amdgpu_buffer_rsrc_t rr = rs;
     uint32_t rej = 0u, rc = 0u;   // rejected in the wave; in its chunks so far
+    int64_t rlo = 0;
+    bool rok_all = false;
     if constexpr (PART) {
       rej = wvalid - wsum;
-      const int64_t rlo = ka.n - (wb - (int64_t)base) - (int64_t)rej;
-      const bool ok = rlo >= 0 && rlo + (int64_t)rej <= ka.n;
-      rr = __builtin_amdgcn_make_buffer_rsrc(static_cast<uint32_t *>(ka.out) + (ok ? rlo : 0), (short)0,
-                                             ok ? (int)(4u * rej) : 0, 0x00020000);
+      rlo = ka.n - (wb - (int64_t)base) - (int64_t)rej;
+      rok_all = rlo >= 0 && rlo + (int64_t)rej <= ka.n;
     }
     // chunk c: scan the lanes' counts, pack the kept elements into the
     // wave's LDS row (wave-private: no barrier; R[c] is free afterwards),
     // write them as one contiguous run
+    // Row of the wave's LDS staging area for chunk c: the kept elements in
+    // order at [0, kept); with PART the rejected ones at [256, 256 + nrej)
+    // in output order (the chunk's last rejected element first, since the
+    // rejected elements fill the output from the end); every other element
+    // (a rejected one without PART, or one past n) in the lane's spare words
+    // at [512, 768).  So every element is written, without a branch.
     auto pack = [&](const int c) -> uint32_t {
-      const uint32_t m = (mask[c / 8] >> (4 * (c % 8))) & 0xfu;
+      uint32_t m = (mask[c / 8] >> (4 * (c % 8))) & 0xfu;
+      // chunk c is packed after chunk c-1 is counted (cb): the chunks' scans
+      // are not all hoisted ahead of the stores, which would hold a scan
+      // result per chunk in registers
+      asm volatile("" : "+v"(m) : "s"(cb));
       const uint32_t x = wave_scan<Op>((uint32_t)__builtin_popcount(m));
       const uint32_t off = lane_up1(x);
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if ((m >> k) & 1u) stage[off + (uint32_t)__builtin_popcount(m & ((1u << k) - 1u))] = R[c][k];
       const uint32_t kc = readlane32(x, 63);
-      if constexpr (PART) {
-        // rejected elements after the kept ones in the row: a valid element
-        // that is not kept has (4 lane + k) - (kept before it) rejected
-        // elements before it in the chunk
+      const int64_t v64 = (int64_t)wvalid - 256 * c;
+      const uint32_t valid = v64 <= 0 ? 0u : (v64 >= 256 ? 256u : (uint32_t)v64);
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if (c * 256 + k < rem && !((m >> k) & 1u))
-            stage[kc + 4u * (uint32_t)lane + (uint32_t)k - off - (uint32_t)__builtin_popcount(m & ((1u << k) - 1u))] =
-                R[c][k];
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t before = (uint32_t)__builtin_popcount(m & ((1u << k) - 1u));
+        const bool kept = (m >> k) & 1u;
+        uint32_t pos = kept ? off + before : 512u + 4u * (uint32_t)lane + (uint32_t)k;
+        if constexpr (PART) {
+          // rank among the chunk's rejected elements: (4 lane + k) - (kept before it)
+          const uint32_t q = 4u * (uint32_t)lane + (uint32_t)k - off - before;
+          if (!kept && c * 256 + k < rem) pos = 256u + (valid - kc) - 1u - q;
+        }
+        stage[pos] = R[c][k];
       }
       return kc;
     };
+    // one 128-bit store per lane: lane l writes row words 4l .. 4l+3 to the
+    // run's words 4l .. 4l+3 through a resource that ends at the run's last
+    // element (the hardware checks every dword, so a lane past the end
+    // writes nothing and the lane at the end only its words inside)
+    const u32x4 *srow = reinterpret_cast<const u32x4 *>(stage);
     auto flush = [&](const int c, const uint32_t kept) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const uint32_t idx = 64u * j + lane;
-        if (idx < kept) __builtin_amdgcn_raw_buffer_store_b32(stage[idx], rs, 4u * (cb + idx), 0, SAUX);
-      }
+      const int64_t kend = (int64_t)cb + kept;
+      const int64_t klim = kbytes < (int64_t)0x7fffffff ? kbytes : (int64_t)0x7fffffff;
+      const int krec = kok ? (int)(4 * kend < klim ? 4 * kend : klim) : 0;
+      const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc(
+          static_cast<uint32_t *>(ka.out) + (kok ? base : 0u), (short)0, krec, 0x00020000);
+      __builtin_amdgcn_raw_buffer_store_b128(srow[lane], rk, 4u * (cb + 4u * (uint32_t)lane), 0, SAUX);
       cb += kept;
       if constexpr (PART) {
-        // row entries [kept, valid) are the chunk's rejected elements in
-        // order; the i-th of the wave goes to out[rlo + rej - 1 - i]
+        // this chunk's rejected run is out[rlo + rej - rc - nrej, rlo + rej - rc)
         const int64_t v64 = (int64_t)wvalid - 256 * c;
         const uint32_t valid = v64 <= 0 ? 0u : (v64 >= 256 ? 256u : (uint32_t)v64);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const uint32_t idx = 64u * j + lane;
-          if (idx >= kept && idx < valid)
-            __builtin_amdgcn_raw_buffer_store_b32(stage[idx], rr, 4u * (rej - 1u - (rc + idx - kept)), 0, SAUX);
-        }
-        rc += valid - kept;
+        const uint32_t nrej = valid - kept;
+        const int64_t r0 = rlo + (int64_t)rej - (int64_t)rc - (int64_t)nrej;
+        const bool rok = rok_all && nrej > 0u;
+        const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(
+            static_cast<uint32_t *>(ka.out) + (rok ? r0 : 0), (short)0, rok ? (int)(4u * nrej) : 0, 0x00020000);
+        __builtin_amdgcn_raw_buffer_store_b128(srow[64 + lane], rq, 16u * (uint32_t)lane, 0, SAUX);
+        rc += nrej;
       }
     };
     // the first half goes out while the next tile is taken from the counter,

@@ -5,10 +5,10 @@
 
 namespace mi355scan {
 
-// 256 threads x 64 elements per tile, [vec]
+// 1024 threads x 64 elements per tile, [vec]
 const CompactKernels kPartition = {
-    256, 64,
-    {(const void *)&compact_tiles<256, 64, false, 3, true>, (const void *)&compact_tiles<256, 64, true, 3, true>},
+    1024, 64,
+    {(const void *)&compact_tiles<1024, 64, false, 4, true>, (const void *)&compact_tiles<1024, 64, true, 4, true>},
     nullptr,
 };
 

@@ -676,7 +676,7 @@ scan_status_t two_pass(const void *in, void *out, int64_t n, scan_dtype_t dt, ui
 }
 
 // Stream compaction fused with the exclusive scan: one resident launch over
-// 16384-element tiles (tiles from the counter, as the scan's mode 1).
+// 65536-element tiles (tiles from the counter, as the scan's mode 1).
 // part: the two-way partition (rejected elements to the end, reversed), which
 // writes ahead of the tiles still to be read and so cannot run in place.
 scan_status_t compact(const void *in, void *out, int64_t n, scan_dtype_t dt, int32_t predicate,

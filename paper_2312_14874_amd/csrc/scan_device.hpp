@@ -388,31 +388,54 @@ typedef const __attribute__((address_space(4))) int64_t k_i64;
 // candidate starts (the common case: segments longer than a tile) reads them
 // with scalar loads and one lane sets the bits; a tile with more falls back
 // to vector loads spread over the workgroup.
-template <int BLOCK, int TILE, int WSPAN, bool REV>
-__device__ uint32_t mark_heads(const KernelArgs &a, int64_t t, uint32_t *heads, uint32_t *flag) {
-  constexpr int kScalarHeads = 8;
-  const int tid = threadIdx.x;
+// A tile's candidate segment starts, read ahead with scalar loads: the range
+// [s_lo, s_hi) of segments from the tile map and, when there are at most
+// kScalarHeads of them (segments longer than a tile, the common case), their
+// offsets.  The map entries of a resident workgroup's next tile are loaded
+// as soon as the tile is taken and the offsets after its loads are issued,
+// so mark_heads does not wait for either at the start of the tile.
+constexpr int kScalarHeads = 8;
+struct HeadsPre {
+  int64_t s_lo, s_hi;
+  int64_t o[kScalarHeads];
+};
+
+template <bool REV>
+__device__ __forceinline__ void heads_map(const KernelArgs &a, int64_t t, HeadsPre &h) {
   // tiles < 2^29, so the uniform tile index fits one scalar register
+  const int pt = __builtin_amdgcn_readfirstlane((int)(REV ? (a.tiles - 1 - t) : t));
+  if (a.tile_seg) {
+    h.s_lo = ((k_u32 *)a.tile_seg)[pt];
+    h.s_hi = ((k_u32 *)a.tile_seg)[pt + 1];
+  } else {
+    h.s_lo = 0;
+    h.s_hi = a.num_segments + 1;
+  }
+}
+
+__device__ __forceinline__ void heads_offsets(const KernelArgs &a, HeadsPre &h) {
+  const int64_t cnt = h.s_hi - h.s_lo;
+  if (a.tile_seg && cnt > 0 && cnt <= kScalarHeads) {
+    // indices clamped into [s_lo, s_hi - 1] so every load stays inside offsets[0..S]
+#pragma unroll
+    for (int k = 0; k < kScalarHeads; ++k) h.o[k] = ((k_i64 *)a.offsets)[h.s_lo + (k < cnt ? k : cnt - 1)];
+  }
+}
+
+template <int BLOCK, int TILE, int WSPAN, bool REV>
+__device__ uint32_t mark_heads(const KernelArgs &a, int64_t t, const HeadsPre &h, uint32_t *heads,
+                               uint32_t *flag) {
+  const int tid = threadIdx.x;
   const int pt = __builtin_amdgcn_readfirstlane((int)(REV ? (a.tiles - 1 - t) : t));
   const int64_t pb = (int64_t)pt * TILE;
   const int64_t rem = a.n - pb;
   const int valid = rem < TILE ? (int)rem : TILE;
   const int shift = REV ? 1 : 0;
-  int64_t s_lo, s_hi;
-  if (a.tile_seg) {
-    s_lo = ((k_u32 *)a.tile_seg)[pt];
-    s_hi = ((k_u32 *)a.tile_seg)[pt + 1];
-  } else {
-    s_lo = 0;
-    s_hi = a.num_segments + 1;
-  }
+  const int64_t s_lo = h.s_lo, s_hi = h.s_hi;
   if (s_hi <= s_lo) return 0u;
   const int64_t cnt = s_hi - s_lo;
   if (a.tile_seg && cnt <= kScalarHeads) {
-    // indices clamped into [s_lo, s_hi - 1] so every load stays inside offsets[0..S]
-    int64_t o[kScalarHeads];
-#pragma unroll
-    for (int k = 0; k < kScalarHeads; ++k) o[k] = ((k_i64 *)a.offsets)[s_lo + (k < cnt ? k : cnt - 1)];
+    const int64_t(&o)[kScalarHeads] = h.o;
     uint32_t waves = 0u;
 #pragma unroll
     for (int k = 0; k < kScalarHeads; ++k) {
@@ -910,6 +933,13 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
 
   u32x4 R[SH::CH];
   if (t < a.tiles) load_tile<SH, NT, REV, VEC>(a, t, wave, lane, R);
+  HeadsPre heads_pre;   // segmented: the current tile's segment starts, read ahead
+  if constexpr (SEG) {
+    if (t < a.tiles) {
+      heads_map<REV>(a, t, heads_pre);
+      heads_offsets(a, heads_pre);
+    }
+  }
 
   for (int it = 0;; ++it) {
     const int slot = it & 1;
@@ -917,7 +947,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
     if (a.stride && tid == 0) st_agent(a.status + (1 - parity) * a.capacity + t, 0ull);
 
     uint32_t head_waves = 0u;   // bit w: wave w's span holds a segment start
-    if constexpr (SEG) head_waves = mark_heads<BLOCK, SH::TILE, SH::WSPAN, REV>(a, t, s_heads, &s_flag);
+    if constexpr (SEG) head_waves = mark_heads<BLOCK, SH::TILE, SH::WSPAN, REV>(a, t, heads_pre, s_heads, &s_flag);
 
     // the tile's loads are in flight: scan in registers, combine the waves
     int fh;
@@ -1012,6 +1042,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
     }
     if (next < a.tiles) {
       const WaveSpan<SH, NT, REV, VEC> in(a.in, a, next, wave, lane);
+      if constexpr (SEG) heads_map<REV>(a, next, heads_pre);
 #pragma unroll
       for (int c = KH; c < SH::CH; ++c) {
         out.store(c, R[c]);
@@ -1019,6 +1050,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
       }
 #pragma unroll
       for (int c = SH::CH - KH; c < SH::CH; ++c) in.load(c, R[c]);
+      if constexpr (SEG) heads_offsets(a, heads_pre);
     } else {
 #pragma unroll
       for (int c = KH; c < SH::CH; ++c) out.store(c, R[c]);

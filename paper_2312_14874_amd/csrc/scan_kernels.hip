@@ -125,11 +125,12 @@ const TwoPassKernels kTwoPass = {
     kTotalsBlock,
 };
 
-// stream compaction: 256 threads x 64 elements per tile, [vec]
+// stream compaction: 1024 threads x 64 elements per tile (one workgroup of
+// sixteen waves per CU), [vec]
 __global__ void set_count(int64_t *p, int64_t v) { *p = v; }
 const CompactKernels kCompact = {
-    256, 64,
-    {(const void *)&compact_tiles<256, 64, false, 3>, (const void *)&compact_tiles<256, 64, true, 3>},
+    1024, 64,
+    {(const void *)&compact_tiles<1024, 64, false, 4>, (const void *)&compact_tiles<1024, 64, true, 4>},
     (const void *)&set_count,
 };
 

@@ -45,7 +45,10 @@ def check(a, predicate, threshold=0, **kw):
 
 
 @pytest.mark.parametrize("dtype", [np.int32, np.uint32, np.float32])
-@pytest.mark.parametrize("n", [1, 100, 16383, 16384, 16385, 5 * 16384 + 777, 1 << 20])
+# tile edges of the compaction kernel (1024 threads x 64 elements) and of an
+# earlier 16384-element shape, ragged chunk and lane ends
+@pytest.mark.parametrize("n", [1, 100, 255, 257, 16383, 16384, 16385, 5 * 16384 + 777, 65535, 65536, 65537,
+                               3 * 65536 + 4095, 1 << 20, (1 << 20) + 13])
 def test_nonzero(dtype, n):
     check(data(n, 4000 + n % 89, dtype), "nonzero")
 

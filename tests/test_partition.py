@@ -12,7 +12,8 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 PRED = {"nonzero": 0, "greater": 1}
-TILE = 256 * 64
+TILE = 1024 * 64   # the partition kernel's tile
+OLD_TILE = 256 * 64
 
 
 def run(a, predicate, threshold=0, misalign=0):
@@ -51,7 +52,8 @@ def check(a, predicate, threshold=0, **kw):
 
 
 @pytest.mark.parametrize("dtype", [np.int32, np.uint32, np.float32])
-@pytest.mark.parametrize("n", [1, 2, 100, 255, 257, TILE - 1, TILE, TILE + 1, 5 * TILE + 777, (1 << 20) + 9])
+@pytest.mark.parametrize("n", [1, 2, 100, 255, 257, OLD_TILE - 1, OLD_TILE + 1, TILE - 1, TILE, TILE + 1, 5 * TILE + 777,
+                               (1 << 20) + 9])
 def test_nonzero(dtype, n):
     check(data(n, 7300 + n % 83, dtype), "nonzero")
 
