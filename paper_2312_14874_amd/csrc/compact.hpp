@@ -17,32 +17,47 @@
 
 namespace mi355scan {
 
-__device__ __forceinline__ bool keep_element(uint32_t x, const CompactArgs &a) {
-  if (a.pred == kPredNonzero) return x != 0u;
-  if (a.dtype == 0) return (int32_t)x > (int32_t)a.thr;
-  if (a.dtype == 1) return x > a.thr;
-  return __builtin_bit_cast(float, x) > __builtin_bit_cast(float, a.thr);   // NaN never kept
+// The predicate as one compare of the element's bits with the threshold's,
+// fixed per kernel: kPkUnsigned (uint32 x > t; "not all bits zero" is x > 0),
+// kPkSigned (int32), kPkFloat (float32; a NaN is never kept).  A predicate
+// read from the arguments per element would branch on it for every element.
+template <int PK>
+__device__ __forceinline__ bool keep_kind(uint32_t x, uint32_t thr) {
+  if constexpr (PK == kPkSigned) return (int32_t)x > (int32_t)thr;
+  else if constexpr (PK == kPkFloat) return __builtin_bit_cast(float, x) > __builtin_bit_cast(float, thr);
+  else return x > thr;
+}
+
+// A value the predicate never keeps: elements past n read as it.
+template <int PK>
+constexpr uint32_t never_kept() {
+  return PK == kPkSigned ? 0x80000000u : (PK == kPkFloat ? 0x7FC00000u : 0u);   // INT32_MIN, NaN, 0
 }
 
 // One tile per iteration of a resident grid (tiles from the device counter,
-// the workspace protocol of scan_tiles).  Per chunk each lane keeps a 4-bit
-// selection mask (8 chunks per register); the tile total needs only the
-// lanes' counts, and a chunk's positions are scanned when it is written.
-// The values stay in R until they are written: per chunk, the wave packs its
-// kept elements into its own LDS row (every element is written somewhere, so
-// no per-element branch) and writes them out as one contiguous run, one
-// 128-bit store per lane, instead of one scattered store per element; as in
-// scan_tiles, the registers a packed chunk frees take the next tile's chunk at
-// once.  The output offsets are wave-uniform and kept in scalar registers:
-// a buffer resource the compiler must treat as per-lane would turn every
-// store into a loop over its distinct values.
+// the workspace protocol of scan_tiles).  Two passes over the tile's values,
+// which stay in registers until they are written:
+//  - count: each lane counts its kept elements per chunk, three chunks to a
+//    word (10 bits each: a chunk keeps at most 256), so one wave scan of a
+//    word gives every lane its offset in three chunks and the chunks' totals;
+//  - pack and write, after the look-back: per chunk, the wave packs its kept
+//    elements into its own LDS row (every element is written somewhere, so
+//    no per-element branch) and writes them as one contiguous run, one
+//    128-bit store per lane, instead of one scattered store per element.
+// The predicate is evaluated once in each pass, one compare per element.
+// Elements past n exist only in the wave that holds n; they are replaced
+// there, once, by a value that is never kept, so no element needs a bound
+// check.  As in scan_tiles, the registers a packed chunk frees take the next
+// tile's chunk at once.  The output offsets are wave-uniform and kept in
+// scalar registers: a buffer resource the compiler must treat as per-lane
+// would turn every store into a loop over its distinct values.
 // Counts of kept elements: 32-bit integer sums whose wave totals are folded
 // from one lane each (no register per wave's total).
 struct OpsCount : OpsU32 {
   static constexpr bool kCombineByLane = true;
 };
 
-template <int BLOCK, int ITEMS, bool VEC, int MINW, bool PART = false>
+template <int BLOCK, int ITEMS, bool VEC, int MINW, bool PART, int PK>
 __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
   using SH = Shape<BLOCK, ITEMS>;
   using Op = OpsCount;
@@ -50,13 +65,13 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
   // store cache policy: non-temporal for compaction; the partition's two
   // output streams write faster through the default policy (measured)
   constexpr int SAUX = PART ? 0 : kNtAux;
-  constexpr int MW = (SH::CH + 7) / 8;   // mask words
+  constexpr int NW = (SH::CH + 2) / 3;   // count words, three chunks each
   __shared__ uint32_t s_wtot[SH::WAVES];
   __shared__ uint32_t s_wflag[SH::WAVES];
   __shared__ uint32_t s_carry;
   __shared__ int64_t s_tile;
   __shared__ uint32_t s_parity;
-  __shared__ __attribute__((aligned(16))) uint32_t s_stage[SH::WAVES][768];   // see pack
+  __shared__ __attribute__((aligned(16))) uint32_t s_stage[SH::WAVES][512];   // see pack
   const KernelArgs &ka = a.k;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -84,29 +99,36 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
     for (int c = 0; c < SH::CH; ++c) in.load(c, R[c]);
   }
   while (t < ka.tiles) {
-    // elements of this lane's group in chunk c exist while c*256 + k < rem
     const int64_t wb = wave_base<false, SH::TILE, SH::WSPAN>(t * (int64_t)SH::TILE, wave);
-    const int64_t rem64 = ka.n - wb - 4 * lane;
-    const int rem = rem64 > SH::WSPAN ? SH::WSPAN : (int)rem64;
-    // first pass: the selection masks and the number kept by the lane; the
-    // positions are recomputed per chunk when the chunk is written, so no
-    // per-chunk offsets are held through the look-back
-    uint32_t mask[MW];
-    uint32_t lane_kept = 0u;
+    const int64_t wvalid64 = ka.n - wb;
+    const uint32_t wvalid = wvalid64 <= 0 ? 0u : (wvalid64 >= SH::WSPAN ? (uint32_t)SH::WSPAN : (uint32_t)wvalid64);
+    if (PK != kPkUnsigned && wvalid < (uint32_t)SH::WSPAN) {
+      // (an unsigned compare never keeps the zeros the loads return past n)
 #pragma unroll
-    for (int w = 0; w < MW; ++w) mask[w] = 0u;
+      for (int c = 0; c < SH::CH; ++c)
 #pragma unroll
-    for (int c = 0; c < SH::CH; ++c) {
-      uint32_t m = 0u;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) m |= (c * 256 + k < rem && keep_element(R[c][k], a)) ? (1u << k) : 0u;
-      mask[c / 8] |= m << (4 * (c % 8));
-      lane_kept += (uint32_t)__builtin_popcount(m);
-      // finish the chunk's bits now: left to itself the compiler keeps every
-      // element's bit in a register of its own until the end of the pass
-      asm volatile("" : "+v"(mask[c / 8]), "+v"(lane_kept));
+        for (int k = 0; k < 4; ++k)
+          if ((uint32_t)(c * 256 + 4 * lane + k) >= wvalid) R[c][k] = never_kept<PK>();
     }
-    const uint32_t wsum = readlane32(wave_scan<Op>(lane_kept), 63);
+    // count pass: xe[w] holds, per chunk of the word, the kept elements of
+    // the chunk in earlier lanes; tot[w] the chunk totals (uniform)
+    uint32_t xe[NW], tot[NW];
+    uint32_t wsum = 0u;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      uint32_t cw = 0u;
+#pragma unroll
+      for (int c = 3 * w; c < 3 * w + 3 && c < SH::CH; ++c) {
+        uint32_t kc = 0u;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) kc += keep_kind<PK>(R[c][k], a.thr) ? 1u : 0u;
+        cw |= kc << (10 * (c - 3 * w));
+      }
+      const uint32_t x = wave_scan<Op>(cw);
+      xe[w] = x - cw;
+      tot[w] = readlane32(x, 63);
+      wsum += (tot[w] & 1023u) + ((tot[w] >> 10) & 1023u) + (tot[w] >> 20);
+    }
     uint32_t wpre, agg, wpref, aggf;
     combine_waves<Op, SH::WAVES>(wave, lane, wsum, 0u, s_wtot, s_wflag, wpre, wpref, agg, aggf);
     if (multi && wave == 0) {
@@ -139,8 +161,6 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
     // partition: the wave's rejected elements go to out[rlo, rlo + rej) in
     // reverse order, rlo = n - (rejected before the wave) - (rejected in it);
     // a range outside [0, n) (only after a look-back that gave up) writes nothing
-    const int64_t wvalid64 = ka.n - wb;
-    const uint32_t wvalid = wvalid64 <= 0 ? 0u : (wvalid64 >= SH::WSPAN ? (uint32_t)SH::WSPAN : (uint32_t)wvalid64);
     uint32_t rej = 0u, rc = 0u;   // rejected in the wave; in its chunks so far
     int64_t rlo = 0;
     bool rok_all = false;
@@ -149,37 +169,32 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
       rlo = ka.n - (wb - (int64_t)base) - (int64_t)rej;
       rok_all = rlo >= 0 && rlo + (int64_t)rej <= ka.n;
     }
-    // chunk c: scan the lanes' counts, pack the kept elements into the
-    // wave's LDS row (wave-private: no barrier; R[c] is free afterwards),
-    // write them as one contiguous run
     // Row of the wave's LDS staging area for chunk c: the kept elements in
-    // order at [0, kept); with PART the rejected ones at [256, 256 + nrej)
-    // in output order (the chunk's last rejected element first, since the
-    // rejected elements fill the output from the end); every other element
-    // (a rejected one without PART, or one past n) in the lane's spare words
-    // at [512, 768).  So every element is written, without a branch.
+    // order at [0, kept).  With PART, a rejected element at chunk index e
+    // goes to 255 + (valid - kept) - e + (kept before it): the valid ones
+    // fill [256, 256 + valid - kept) in output order (the chunk's last
+    // rejected element first, since the rejected elements fill the output
+    // from the end); for one past n, (kept before it) is the chunk's whole
+    // count, so it lands in [valid, 256), which no kept element uses.  Without PART a rejected element goes to the lane's spare word
+    // 256 + 64k + lane.  So every element is written, without a branch.
     auto pack = [&](const int c) -> uint32_t {
-      uint32_t m = (mask[c / 8] >> (4 * (c % 8))) & 0xfu;
-      // chunk c is packed after chunk c-1 is counted (cb): the chunks' scans
-      // are not all hoisted ahead of the stores, which would hold a scan
-      // result per chunk in registers
-      asm volatile("" : "+v"(m) : "s"(cb));
-      const uint32_t x = wave_scan<Op>((uint32_t)__builtin_popcount(m));
-      const uint32_t off = lane_up1(x);
-      const uint32_t kc = readlane32(x, 63);
+      const uint32_t sh = 10u * (uint32_t)(c % 3);
+      uint32_t p = (xe[c / 3] >> sh) & 1023u;   // this lane's first kept position
+      const uint32_t kc = (tot[c / 3] >> sh) & 1023u;
+      // chunk c is packed after chunk c-1 is counted (cb): the chunks'
+      // positions are not all hoisted ahead of the stores; and the values
+      // are compared again here rather than the count pass's results (a
+      // lane mask per element) being kept through the look-back
+      asm volatile("" : "+v"(p), "+v"(R[c]) : "s"(cb));
       const int64_t v64 = (int64_t)wvalid - 256 * c;
       const uint32_t valid = v64 <= 0 ? 0u : (v64 >= 256 ? 256u : (uint32_t)v64);
+      const uint32_t rbase = 255u + (valid - kc) - 4u * (uint32_t)lane;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const uint32_t before = (uint32_t)__builtin_popcount(m & ((1u << k) - 1u));
-        const bool kept = (m >> k) & 1u;
-        uint32_t pos = kept ? off + before : 512u + 4u * (uint32_t)lane + (uint32_t)k;
-        if constexpr (PART) {
-          // rank among the chunk's rejected elements: (4 lane + k) - (kept before it)
-          const uint32_t q = 4u * (uint32_t)lane + (uint32_t)k - off - before;
-          if (!kept && c * 256 + k < rem) pos = 256u + (valid - kc) - 1u - q;
-        }
-        stage[pos] = R[c][k];
+        const bool kept = keep_kind<PK>(R[c][k], a.thr);
+        const uint32_t other = PART ? rbase - (uint32_t)k + p : 256u + 64u * (uint32_t)k + (uint32_t)lane;
+        stage[kept ? p : other] = R[c][k];
+        p += kept ? 1u : 0u;
       }
       return kc;
     };

@@ -5,10 +5,12 @@
 
 namespace mi355scan {
 
-// 1024 threads x 64 elements per tile, [vec]
+// 1024 threads x 64 elements per tile, [predicate kind][vec]
+#define MI355SCAN_PARTITION(PK) \
+  { (const void *)&compact_tiles<1024, 64, false, 4, true, PK>, (const void *)&compact_tiles<1024, 64, true, 4, true, PK> }
 const CompactKernels kPartition = {
     1024, 64,
-    {(const void *)&compact_tiles<1024, 64, false, 4, true>, (const void *)&compact_tiles<1024, 64, true, 4, true>},
+    {MI355SCAN_PARTITION(kPkUnsigned), MI355SCAN_PARTITION(kPkSigned), MI355SCAN_PARTITION(kPkFloat)},
     nullptr,
 };
 

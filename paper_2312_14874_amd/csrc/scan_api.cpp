@@ -710,7 +710,11 @@ scan_status_t compact(const void *in, void *out, int64_t n, scan_dtype_t dt, int
     s = stream_ws(dev, stream, T, &ws);
     if (s != SCAN_SUCCESS) return s;
   }
-  const void *fn = K.tiles[((uintptr_t)in & 15u) == 0 ? 1 : 0];
+  // the predicate as the kernel's one compare: "nonzero" is an unsigned x > 0
+  int kind = kPkUnsigned;
+  if (predicate == SCAN_PRED_GREATER) kind = dt == SCAN_I32 ? kPkSigned : (dt == SCAN_F32 ? kPkFloat : kPkUnsigned);
+  const uint32_t thr = predicate == SCAN_PRED_GREATER ? threshold : 0u;
+  const void *fn = K.tiles[kind][((uintptr_t)in & 15u) == 0 ? 1 : 0];
   const int64_t grid = std::min<int64_t>(T, resident_grid(fn, K.block, di.cus, 0, 100));
   CompactArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -728,9 +732,7 @@ scan_status_t compact(const void *in, void *out, int64_t n, scan_dtype_t dt, int
   }
   a.k.err = ws ? ws->err : nullptr;
   a.count = count;
-  a.thr = threshold;
-  a.pred = predicate;
-  a.dtype = (int32_t)dt;
+  a.thr = thr;
   void *args[] = {&a};
   hipError_t e = hipLaunchKernel(fn, dim3((unsigned)grid), dim3(K.block), args, 0, stream);
   return e == hipSuccess ? SCAN_SUCCESS : hip_fail(e);

@@ -126,11 +126,13 @@ const TwoPassKernels kTwoPass = {
 };
 
 // stream compaction: 1024 threads x 64 elements per tile (one workgroup of
-// sixteen waves per CU), [vec]
+// sixteen waves per CU), [predicate kind][vec]
 __global__ void set_count(int64_t *p, int64_t v) { *p = v; }
+#define MI355SCAN_COMPACT(PART, PK) \
+  { (const void *)&compact_tiles<1024, 64, false, 4, PART, PK>, (const void *)&compact_tiles<1024, 64, true, 4, PART, PK> }
 const CompactKernels kCompact = {
     1024, 64,
-    {(const void *)&compact_tiles<1024, 64, false, 4>, (const void *)&compact_tiles<1024, 64, true, 4>},
+    {MI355SCAN_COMPACT(false, kPkUnsigned), MI355SCAN_COMPACT(false, kPkSigned), MI355SCAN_COMPACT(false, kPkFloat)},
     (const void *)&set_count,
 };
 

@@ -64,13 +64,16 @@ struct TwoPassArgs {
 // each element) and kernel arguments.
 constexpr int kPredNonzero = 0;   // keep x whose 32 bits are not all zero
 constexpr int kPredGreater = 1;   // keep x > threshold (typed compare)
+// The compare a compaction kernel is built for: the predicate and the dtype
+// reduce to one of these (kPredNonzero is an unsigned x > 0).
+constexpr int kPkUnsigned = 0;
+constexpr int kPkSigned = 1;
+constexpr int kPkFloat = 2;
 
 struct CompactArgs {
   KernelArgs k;       // in, out, n, tiles, workspace, counter mode fields
   int64_t *count;     // device: number of kept elements, written by the last tile
-  uint32_t thr;       // threshold bits (kPredGreater)
-  int32_t pred;       // kPred*
-  int32_t dtype;      // 0 int32, 1 uint32, 2 float32
+  uint32_t thr;       // threshold bits of the kernel's compare (kPk*): x > thr
 };
 
 // Ordered launches count published tiles in kPubSlots counters per parity

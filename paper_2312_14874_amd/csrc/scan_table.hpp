@@ -53,8 +53,8 @@ extern const TwoPassKernels kTwoPass;
 // Stream compaction fused with the exclusive scan, one tile shape.
 struct CompactKernels {
   int block, items;
-  const void *tiles[2];    // [vec]
-  const void *set_count;   // writes the count when there is nothing to scan
+  const void *tiles[3][2];   // [predicate kind kPk*][vec]
+  const void *set_count;     // writes the count when there is nothing to scan
 };
 extern const CompactKernels kCompact;
 extern const CompactKernels kPartition;   // two-way partition (set_count unused)
