@@ -57,7 +57,7 @@ struct OpsCount : OpsU32 {
   static constexpr bool kCombineByLane = true;
 };
 
-template <int BLOCK, int ITEMS, bool VEC, int MINW, bool PART, int PK>
+template <int BLOCK, int ITEMS, bool VEC, int MINW, bool PART, int PK, int FL>
 __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
   using SH = Shape<BLOCK, ITEMS>;
   using Op = OpsCount;
@@ -66,12 +66,14 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
   // output streams write faster through the default policy (measured)
   constexpr int SAUX = PART ? 0 : kNtAux;
   constexpr int NW = (SH::CH + 2) / 3;   // count words, three chunks each
+  constexpr int KR = FL * 256;           // a group of FL chunks is written as one run
+  static_assert((SH::CH / 2) % FL == 0, "groups tile each half of the wave span");
   __shared__ uint32_t s_wtot[SH::WAVES];
   __shared__ uint32_t s_wflag[SH::WAVES];
   __shared__ uint32_t s_carry;
   __shared__ int64_t s_tile;
   __shared__ uint32_t s_parity;
-  __shared__ __attribute__((aligned(16))) uint32_t s_stage[SH::WAVES][512];   // see pack
+  __shared__ __attribute__((aligned(16))) uint32_t s_stage[SH::WAVES][KR + (PART ? KR : 256)];   // see pack
   const KernelArgs &ka = a.k;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -169,66 +171,93 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
       rlo = ka.n - (wb - (int64_t)base) - (int64_t)rej;
       rok_all = rlo >= 0 && rlo + (int64_t)rej <= ka.n;
     }
-    // Row of the wave's LDS staging area for chunk c: the kept elements in
-    // order at [0, kept).  With PART, a rejected element at chunk index e
-    // goes to 255 + (valid - kept) - e + (kept before it): the valid ones
-    // fill [256, 256 + valid - kept) in output order (the chunk's last
-    // rejected element first, since the rejected elements fill the output
-    // from the end); for one past n, (kept before it) is the chunk's whole
-    // count, so it lands in [valid, 256), which no kept element uses.  Without PART a rejected element goes to the lane's spare word
-    // 256 + 64k + lane.  So every element is written, without a branch.
-    auto pack = [&](const int c) -> uint32_t {
-      const uint32_t sh = 10u * (uint32_t)(c % 3);
-      uint32_t p = (xe[c / 3] >> sh) & 1023u;   // this lane's first kept position
-      const uint32_t kc = (tot[c / 3] >> sh) & 1023u;
-      // chunk c is packed after chunk c-1 is counted (cb): the chunks'
-      // positions are not all hoisted ahead of the stores; and the values
-      // are compared again here rather than the count pass's results (a
-      // lane mask per element) being kept through the look-back
-      asm volatile("" : "+v"(p), "+v"(R[c]) : "s"(cb));
-      const int64_t v64 = (int64_t)wvalid - 256 * c;
-      const uint32_t valid = v64 <= 0 ? 0u : (v64 >= 256 ? 256u : (uint32_t)v64);
-      const uint32_t rbase = 255u + (valid - kc) - 4u * (uint32_t)lane;
+    // The chunks go in groups of FL, each group written as one run.  Row of
+    // the wave's LDS staging area for a group: its kept elements in order at
+    // [0, kept).  With PART, a rejected element at group index e goes to
+    // KR - 1 + (valid - kept) - e + (kept before it), valid and kept being
+    // the group's: the valid ones fill [KR, KR + valid - kept) in output
+    // order (the group's last rejected element first, since the rejected
+    // elements fill the output from the end); for one past n, (kept before
+    // it) is the group's whole count, so it lands in [valid, KR), which no
+    // kept element uses.  Without PART a rejected element goes to the lane's
+    // spare word KR + 64k + lane.  So every element is written, without a
+    // branch.
+    auto field = [&](const uint32_t (&w)[NW], const int c) -> uint32_t {
+      return (w[c / 3] >> (10u * (uint32_t)(c % 3))) & 1023u;
+    };
+    // pack chunk c of a group: cg kept in the group's earlier chunks
+    // (uniform), rb = KR - 1 + (valid - kept) - 256 (c - first chunk)
+    auto pack = [&](const int c, const uint32_t cg, const uint32_t rb) {
+      uint32_t p = cg + field(xe, c);   // this lane's first kept position
+      // chunk c is packed after the previous one is counted (cg): the
+      // chunks' positions are not all hoisted ahead of the stores; and the
+      // values are compared again here rather than the count pass's results
+      // (a lane mask per element) being kept through the look-back
+      asm volatile("" : "+v"(p), "+v"(R[c]) : "s"(cg));
+      const uint32_t rbase = rb - 4u * (uint32_t)lane;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const bool kept = keep_kind<PK>(R[c][k], a.thr);
-        const uint32_t other = PART ? rbase - (uint32_t)k + p : 256u + 64u * (uint32_t)k + (uint32_t)lane;
+        const uint32_t other = PART ? rbase - (uint32_t)k + p : (uint32_t)KR + 64u * (uint32_t)k + (uint32_t)lane;
         stage[kept ? p : other] = R[c][k];
         p += kept ? 1u : 0u;
       }
-      return kc;
     };
-    // one 128-bit store per lane: lane l writes row words 4l .. 4l+3 to the
-    // run's words 4l .. 4l+3 through a resource that ends at the run's last
-    // element (the hardware checks every dword, so a lane past the end
-    // writes nothing and the lane at the end only its words inside)
+    // FL 128-bit stores per lane and run: lane l writes row words 4l .. 4l+3
+    // (+256 i) to the run's words 4l .. 4l+3 (+256 i) through a resource that
+    // ends at the run's last element (the hardware checks every dword, so a
+    // lane past the end writes nothing and the lane at the end only its
+    // words inside)
     const u32x4 *srow = reinterpret_cast<const u32x4 *>(stage);
-    auto flush = [&](const int c, const uint32_t kept) {
+    auto flush = [&](const uint32_t kept, const uint32_t valid) {
       const int64_t kend = (int64_t)cb + kept;
       const int64_t klim = kbytes < (int64_t)0x7fffffff ? kbytes : (int64_t)0x7fffffff;
       const int krec = kok ? (int)(4 * kend < klim ? 4 * kend : klim) : 0;
       const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc(
           static_cast<uint32_t *>(ka.out) + (kok ? base : 0u), (short)0, krec, 0x00020000);
-      __builtin_amdgcn_raw_buffer_store_b128(srow[lane], rk, 4u * (cb + 4u * (uint32_t)lane), 0, SAUX);
+#pragma unroll
+      for (int i = 0; i < FL; ++i)
+        __builtin_amdgcn_raw_buffer_store_b128(srow[64 * i + lane], rk, 4u * (cb + 256u * i + 4u * (uint32_t)lane),
+                                               0, SAUX);
       cb += kept;
       if constexpr (PART) {
-        // this chunk's rejected run is out[rlo + rej - rc - nrej, rlo + rej - rc)
-        const int64_t v64 = (int64_t)wvalid - 256 * c;
-        const uint32_t valid = v64 <= 0 ? 0u : (v64 >= 256 ? 256u : (uint32_t)v64);
+        // this group's rejected run is out[rlo + rej - rc - nrej, rlo + rej - rc)
         const uint32_t nrej = valid - kept;
         const int64_t r0 = rlo + (int64_t)rej - (int64_t)rc - (int64_t)nrej;
         const bool rok = rok_all && nrej > 0u;
         const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(
             static_cast<uint32_t *>(ka.out) + (rok ? r0 : 0), (short)0, rok ? (int)(4u * nrej) : 0, 0x00020000);
-        __builtin_amdgcn_raw_buffer_store_b128(srow[64 + lane], rq, 16u * (uint32_t)lane, 0, SAUX);
+#pragma unroll
+        for (int i = 0; i < FL; ++i)
+          __builtin_amdgcn_raw_buffer_store_b128(srow[KR / 4 + 64 * i + lane], rq, 1024u * i + 16u * (uint32_t)lane,
+                                                 0, SAUX);
         rc += nrej;
       }
     };
-    // the first half goes out while the next tile is taken from the counter,
-    // then each chunk's registers take the next tile's chunk once it is packed
+    // group g0 .. g0+FL-1; with `in`, each chunk's registers take the next
+    // tile's chunk c - KH once the chunk is packed
     constexpr int KH = SH::CH / 2;
+    using Span = WaveSpan<SH, true, false, VEC>;
+    auto group = [&](const int g0, auto load, const Span &in) {
+      uint32_t kg = 0u;
 #pragma unroll
-    for (int c = 0; c < KH; ++c) flush(c, pack(c));
+      for (int j = 0; j < FL; ++j) kg += field(tot, g0 + j);
+      const int64_t v64 = (int64_t)wvalid - 256 * g0;
+      const uint32_t valid = v64 <= 0 ? 0u : (v64 >= KR ? (uint32_t)KR : (uint32_t)v64);
+      uint32_t cg = 0u;
+#pragma unroll
+      for (int j = 0; j < FL; ++j) {
+        pack(g0 + j, cg, (uint32_t)(KR - 1) + (valid - kg) - 256u * (uint32_t)j);
+        cg += field(tot, g0 + j);
+        if constexpr (decltype(load)::value) in.load(g0 + j - KH, R[g0 + j - KH]);
+      }
+      flush(kg, valid);
+    };
+    // the first half goes out while the next tile is taken from the counter,
+    // then the second half's registers take the next tile's chunks
+    const Span cur(ka.in, ka, t, wave, lane);   // (not read: the first half loads nothing)
+#pragma unroll
+    for (int g0 = 0; g0 < KH; g0 += FL) group(g0, std::false_type{}, cur);
     int64_t next = ka.tiles;
     if (multi) {
       if (wave == 0) {
@@ -239,18 +268,14 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
       next = s_tile;
     }
     if (next < ka.tiles) {
-      const WaveSpan<SH, true, false, VEC> in(ka.in, ka, next, wave, lane);
+      const Span in(ka.in, ka, next, wave, lane);
 #pragma unroll
-      for (int c = KH; c < SH::CH; ++c) {
-        const uint32_t kept = pack(c);
-        in.load(c - KH, R[c - KH]);
-        flush(c, kept);
-      }
+      for (int g0 = KH; g0 < SH::CH; g0 += FL) group(g0, std::true_type{}, in);
 #pragma unroll
       for (int c = SH::CH - KH; c < SH::CH; ++c) in.load(c, R[c]);
     } else {
 #pragma unroll
-      for (int c = KH; c < SH::CH; ++c) flush(c, pack(c));
+      for (int g0 = KH; g0 < SH::CH; g0 += FL) group(g0, std::false_type{}, cur);
     }
     t = next;
   }

@@ -126,13 +126,15 @@ const TwoPassKernels kTwoPass = {
 };
 
 // stream compaction: 1024 threads x 64 elements per tile (one workgroup of
-// sixteen waves per CU), [predicate kind][vec]
+// sixteen waves per CU), kept elements written in runs of four chunks,
+// [predicate kind][vec]
 __global__ void set_count(int64_t *p, int64_t v) { *p = v; }
-#define MI355SCAN_COMPACT(PART, PK) \
-  { (const void *)&compact_tiles<1024, 64, false, 4, PART, PK>, (const void *)&compact_tiles<1024, 64, true, 4, PART, PK> }
+#define MI355SCAN_COMPACT(PK) \
+  { (const void *)&compact_tiles<1024, 64, false, 4, false, PK, 4>, \
+    (const void *)&compact_tiles<1024, 64, true, 4, false, PK, 4> }
 const CompactKernels kCompact = {
     1024, 64,
-    {MI355SCAN_COMPACT(false, kPkUnsigned), MI355SCAN_COMPACT(false, kPkSigned), MI355SCAN_COMPACT(false, kPkFloat)},
+    {MI355SCAN_COMPACT(kPkUnsigned), MI355SCAN_COMPACT(kPkSigned), MI355SCAN_COMPACT(kPkFloat)},
     (const void *)&set_count,
 };
 

@@ -64,6 +64,14 @@ def test_greater(dtype, thr):
     check(data(3 * TILE + 99, 7400, dtype, zero_frac=0.1), "greater", thr)
 
 
+# several tiles with a ragged last one: past n the loads read zeros, which a
+# signed or float compare with a negative threshold would keep
+@pytest.mark.parametrize("dtype,thr", [(np.int32, -1 << 30), (np.int32, -1), (np.float32, -3.0), (np.uint32, 0)])
+@pytest.mark.parametrize("n", [5 * TILE + 777, 3 * TILE + 4096 * 7 + 1283])
+def test_greater_ragged_tiles(dtype, thr, n):
+    check(data(n, 4150 + n % 97, dtype, zero_frac=0.1), "greater", thr)
+
+
 @pytest.mark.parametrize("zero_frac", [0.0, 1.0, 0.999, 0.001])
 def test_selectivity_extremes(zero_frac):
     check(data(7 * TILE + 5, 7500, np.int32, zero_frac=zero_frac), "nonzero")
