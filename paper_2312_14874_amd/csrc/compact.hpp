@@ -234,11 +234,11 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
         rc += nrej;
       }
     };
-    // group g0 .. g0+FL-1; with `in`, each chunk's registers take the next
-    // tile's chunk c - KH once the chunk is packed
+    // group g0 .. g0+FL-1; given the next tile's span (not nullptr), each
+    // chunk's registers take the next tile's chunk c - KH once it is packed
     constexpr int KH = SH::CH / 2;
     using Span = WaveSpan<SH, true, false, VEC>;
-    auto group = [&](const int g0, auto load, const Span &in) {
+    auto group = [&](const int g0, const auto in) {
       uint32_t kg = 0u;
 #pragma unroll
       for (int j = 0; j < FL; ++j) kg += field(tot, g0 + j);
@@ -249,15 +249,14 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
       for (int j = 0; j < FL; ++j) {
         pack(g0 + j, cg, (uint32_t)(KR - 1) + (valid - kg) - 256u * (uint32_t)j);
         cg += field(tot, g0 + j);
-        if constexpr (decltype(load)::value) in.load(g0 + j - KH, R[g0 + j - KH]);
+        if constexpr (std::is_pointer_v<decltype(in)>) in->load(g0 + j - KH, R[g0 + j - KH]);
       }
       flush(kg, valid);
     };
     // the first half goes out while the next tile is taken from the counter,
     // then the second half's registers take the next tile's chunks
-    const Span cur(ka.in, ka, t, wave, lane);   // (not read: the first half loads nothing)
 #pragma unroll
-    for (int g0 = 0; g0 < KH; g0 += FL) group(g0, std::false_type{}, cur);
+    for (int g0 = 0; g0 < KH; g0 += FL) group(g0, nullptr);
     int64_t next = ka.tiles;
     if (multi) {
       if (wave == 0) {
@@ -270,12 +269,12 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
     if (next < ka.tiles) {
       const Span in(ka.in, ka, next, wave, lane);
 #pragma unroll
-      for (int g0 = KH; g0 < SH::CH; g0 += FL) group(g0, std::true_type{}, in);
+      for (int g0 = KH; g0 < SH::CH; g0 += FL) group(g0, &in);
 #pragma unroll
       for (int c = SH::CH - KH; c < SH::CH; ++c) in.load(c, R[c]);
     } else {
 #pragma unroll
-      for (int g0 = KH; g0 < SH::CH; g0 += FL) group(g0, std::false_type{}, cur);
+      for (int g0 = KH; g0 < SH::CH; g0 += FL) group(g0, nullptr);
     }
     t = next;
   }
