@@ -72,6 +72,23 @@ def test_greater_ragged_tiles(dtype, thr, n):
     check(data(n, 4150 + n % 97, dtype, zero_frac=0.1), "greater", thr)
 
 
+# thresholds at the ends of each type's range, with those values (and, for
+# float32, infinities, NaN and both zeros) in the data; several tiles and a
+# ragged last one, where the elements past n read as a value never kept
+@pytest.mark.parametrize("dtype,thr", [(np.int32, int(np.iinfo(np.int32).min)), (np.int32, int(np.iinfo(np.int32).max)),
+                                       (np.uint32, 0), (np.uint32, int(np.iinfo(np.uint32).max)),
+                                       (np.float32, -np.inf), (np.float32, np.inf), (np.float32, np.nan)])
+def test_greater_extreme_thresholds(dtype, thr):
+    a = data(4 * TILE + 3 * 4096 + 517, 4160, dtype, zero_frac=0.1)
+    if dtype == np.float32:
+        specials = np.array([np.inf, -np.inf, np.nan, 0.0, -0.0], dtype=np.float32)
+    else:
+        info = np.iinfo(dtype)
+        specials = np.array([info.min, info.max, 0, 1, info.max - 1], dtype=dtype)
+    a[::97] = np.resize(specials, a[::97].size)
+    check(a, "greater", thr)
+
+
 @pytest.mark.parametrize("zero_frac", [0.0, 1.0, 0.999, 0.001])
 def test_selectivity_extremes(zero_frac):
     check(data(7 * TILE + 5, 7500, np.int32, zero_frac=zero_frac), "nonzero")
