@@ -47,10 +47,16 @@ struct OpsU32 {
   // each from LDS into registers of its own (false); measured per type: the
   // float64 totals spill the 768 x 128 kernel in the second form
   static constexpr bool kCombineByLane = false;
+  // the operator has an inverse (lsub, csub): a segmented scan then runs the
+  // plain scan and takes away, from each element at or after a segment start,
+  // the plain prefix before that start (exact in wrapping arithmetic)
+  static constexpr bool kInverse = true;
   __device__ static lane_t lzero() { return 0u; }
   __device__ static carry_t czero() { return 0u; }
   __device__ static lane_t ladd(lane_t a, lane_t b) { return a + b; }
   __device__ static carry_t cadd(carry_t a, carry_t b) { return a + b; }
+  __device__ static lane_t lsub(lane_t a, lane_t b) { return a - b; }
+  __device__ static carry_t csub(carry_t a, carry_t b) { return a - b; }
   __device__ static carry_t widen(lane_t x) { return x; }
   __device__ static lane_t narrow(carry_t x) { return x; }
   __device__ static uint32_t lbits(lane_t x) { return x; }
@@ -76,6 +82,7 @@ struct OpsF32 {
   static constexpr int kSegGroup = 2;
   static constexpr bool kSplitCarry = false;
   static constexpr bool kCombineByLane = true;
+  static constexpr bool kInverse = false;   // rounding: restarts, not differences
   __device__ static lane_t lzero() { return 0.0f; }
   __device__ static carry_t czero() { return 0.0; }
   __device__ static lane_t ladd(lane_t a, lane_t b) { return a + b; }
@@ -103,6 +110,7 @@ struct OpsF32 {
 //   The key is applied to a chunk before its scan and removed after the carry.
 struct OpsMaxU32 : OpsU32 {
   static constexpr bool kKeyed = true;
+  static constexpr bool kInverse = false;
   __device__ static lane_t ladd(lane_t a, lane_t b) { return a > b ? a : b; }
   __device__ static carry_t cadd(carry_t a, carry_t b) { return a > b ? a : b; }
 };
@@ -110,6 +118,8 @@ struct OpsMaxU32 : OpsU32 {
 struct OpsXorU32 : OpsU32 {
   __device__ static lane_t ladd(lane_t a, lane_t b) { return a ^ b; }
   __device__ static carry_t cadd(carry_t a, carry_t b) { return a ^ b; }
+  __device__ static lane_t lsub(lane_t a, lane_t b) { return a ^ b; }
+  __device__ static carry_t csub(carry_t a, carry_t b) { return a ^ b; }
 };
 
 // ------------------------------------------------------------ memory helpers
@@ -740,6 +750,97 @@ __device__ __forceinline__ void scan_wave(uint32_t exclusive, uint32_t key, int 
 }
 
 
+// Segment starts by subtraction (operators with an inverse).  For a wave
+// whose span holds a segment start, after the plain scan_wave (R: the plain
+// wave-local prefixes, inclusive or exclusive; wsum: the wave's total) and
+// the plain carry add (R += win everywhere): an element at or after a start h
+// takes away S_h, the carried plain prefix of the elements before h
+// (exclusive: the value at h; inclusive: the value just before h, which for
+// h = 0 is the carry into the wave), which leaves the scan of its segment;
+// elements before the first start keep the carry.  Per chunk the lane finds
+// the S of its latest start at or before each element, a segmented lane scan
+// brings the latest start's S of earlier lanes, and each chunk passes the
+// latest S on to the next (SegRun, wave-uniform).  It runs chunk by chunk as
+// the tile is stored, so that only the chunk being stored passes through the
+// branch: a branch over every register of the tile (the segmented carry add
+// beside the plain one, or this correction as one pass) makes the
+// segmented kernel spill.
+template <class Op>
+struct SegRun {
+  typename Op::lane_t run;         // S of the wave's latest start so far (none: the identity)
+  typename Op::lane_t prev_last;   // the value before the next chunk's first element
+};
+template <class Op, class SH, bool REV>
+__device__ __forceinline__ void seg_subtract_chunk(int c, bool ex, int wave, int lane, const uint32_t *heads,
+                                                   u32x4 &r, SegRun<Op> &sr) {
+  using lane_t = typename Op::lane_t;
+  constexpr int p0 = REV ? 3 : 0, p1 = REV ? 2 : 1, p2 = REV ? 1 : 2, p3 = REV ? 0 : 3;
+  constexpr int ph[4] = {p0, p1, p2, p3};
+  const uint32_t *hw = heads + ((wave * SH::WSPAN + lane * 4) >> 5);
+  const uint32_t hb = (hw[c * 8] >> ((lane * 4) & 31)) & 0xfu;   // bit k: a start at logical element k
+  lane_t v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = Op::lfrom(r[ph[k]]);
+  // S at a start at k, and the S of the lane's latest start at or before k
+  const lane_t up = Op::lfrom(lane_up1(Op::lbits(v[3])));
+  lane_t ls[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const lane_t before = k > 0 ? v[k > 0 ? k - 1 : 0] : (lane == 0 ? sr.prev_last : up);
+    const lane_t sk = ex ? v[k] : before;
+    ls[k] = ((hb >> k) & 1u) ? sk : (k > 0 ? ls[k > 0 ? k - 1 : 0] : Op::lzero());
+  }
+  // lanes with a start carry the S of their latest one; the segmented scan
+  // gives each lane the S of the latest start in lanes <= l (f: any)
+  lane_t x = hb ? ls[3] : Op::lzero();
+  uint32_t f = hb != 0u;
+  wave_scan_seg<Op>(x, f);
+  const lane_t xin = Op::lfrom(lane_up1(Op::lbits(x)));
+  const lane_t incoming = lane_up1(f) ? xin : sr.run;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const lane_t sub = (hb & ((2u << k) - 1u)) ? ls[k] : incoming;
+    r[ph[k]] = Op::lbits(Op::lsub(v[k], sub));
+  }
+  if (readlane32(f, 63)) sr.run = Op::lfrom(readlane32(Op::lbits(x), 63));
+  sr.prev_last = Op::lfrom(readlane32(Op::lbits(v[3]), 63));
+}
+
+// The plain wave-local prefix before the wave's last segment start (the
+// start's exclusive value): the wave's total minus it is the total since that
+// start, which the wave contributes to the tile aggregate.  Reads R only.
+template <class Op, class SH, bool REV>
+__device__ __forceinline__ typename Op::lane_t seg_last_prefix(bool ex, int wave, int lane, const uint32_t *heads,
+                                                               const u32x4 (&R)[SH::CH]) {
+  using lane_t = typename Op::lane_t;
+  constexpr int p0 = REV ? 3 : 0, p1 = REV ? 2 : 1, p2 = REV ? 1 : 2, p3 = REV ? 0 : 3;
+  constexpr int ph[4] = {p0, p1, p2, p3};
+  const uint32_t *hw = heads + ((wave * SH::WSPAN + lane * 4) >> 5);
+  const int hs = (lane * 4) & 31;
+  // the last start's logical position (uniform; the wave holds one)
+  int last = -1;
+#pragma unroll
+  for (int c = 0; c < SH::CH; ++c) {
+    const uint32_t hb = (hw[c * 8] >> hs) & 0xfu;
+    const uint64_t hm = ballot(hb != 0u);
+    if (hm != 0ull) {
+      const int l = 63 - __builtin_clzll(hm);
+      last = c * 256 + l * 4 + (31 - __builtin_clz(__builtin_amdgcn_readlane(hb, l)));
+    }
+  }
+  // exclusive: the value at the start; inclusive: the value before it
+  const int at = ex ? last : last - 1;
+  if (at < 0) return Op::lzero();
+  const int tc = at >> 8, tl = (at & 255) >> 2, tk = at & 3;
+  uint32_t val = 0u;
+#pragma unroll
+  for (int c = 0; c < SH::CH; ++c)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (c == tc && k == tk) val = readlane32(R[c][ph[k]], tl);
+  return Op::lfrom(val);
+}
+
 // Wave totals through LDS: this wave's exclusive prefix (wpre, wpref) and
 // the tile aggregate (agg, aggf), all folded left to right.  Contains one
 // barrier.  With Op::kCombineByLane lane w reads wave w's total and the fold
@@ -895,7 +996,10 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
   __shared__ int64_t s_tile[2];
   __shared__ uint64_t s_clear_hi;
   __shared__ uint32_t s_parity, s_flag;
-  __shared__ uint32_t s_heads[SEG ? SH::TILE / 32 : 1];
+  // segment starts of the tile, one bit per element; two, alternating by
+  // tile: a wave may still read the last tile's bits while it stores (the
+  // subtraction of segmented scans) when another wave marks the next tile's
+  __shared__ uint32_t s_heads[2][SEG ? SH::TILE / 32 : 1];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -947,14 +1051,14 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
     if (a.stride && tid == 0) st_agent(a.status + (1 - parity) * a.capacity + t, 0ull);
 
     uint32_t head_waves = 0u;   // bit w: wave w's span holds a segment start
-    if constexpr (SEG) head_waves = mark_heads<BLOCK, SH::TILE, SH::WSPAN, REV>(a, t, heads_pre, s_heads, &s_flag);
+    if constexpr (SEG) head_waves = mark_heads<BLOCK, SH::TILE, SH::WSPAN, REV>(a, t, heads_pre, s_heads[slot], &s_flag);
 
     // the tile's loads are in flight: scan in registers, combine the waves
     int fh;
     carry_t wsum, wpre, agg;
     uint32_t wflag, wpref, aggf;
     bool first_is_head = false;
-    if constexpr (SEG) first_is_head = (head_waves & 1u) && (s_heads[0] & 1u);
+    if constexpr (SEG) first_is_head = (head_waves & 1u) && (s_heads[slot][0] & 1u);
     const bool need_carry = t > 0 && !first_is_head;
     if constexpr (kEarly) {
       // lane partials of every chunk as it arrives, and the lane total
@@ -993,8 +1097,19 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
         if (lane == 0) s_carry[slot] = carry;
       }
     } else {
-      scan_wave<Op, SH, SEG, REV>(a.exclusive, a.key, wave, lane, (head_waves >> wave) & 1u, s_heads, R, fh,
-                                  wsum, wflag);
+      if constexpr (SEG && Op::kInverse) {
+        // the flat scan's code for every wave; a wave that holds a segment
+        // start contributes its total since the last one (the elements are
+        // corrected after the carry, by seg_subtract)
+        scan_wave<Op, SH, false, REV>(a.exclusive, a.key, wave, lane, false, s_heads[slot], R, fh, wsum, wflag);
+        if ((head_waves >> wave) & 1u) {
+          wsum = Op::csub(wsum, Op::widen(seg_last_prefix<Op, SH, REV>(a.exclusive != 0u, wave, lane, s_heads[slot], R)));
+          wflag = 1u;
+        }
+      } else {
+        scan_wave<Op, SH, SEG, REV>(a.exclusive, a.key, wave, lane, (head_waves >> wave) & 1u, s_heads[slot], R, fh,
+                                    wsum, wflag);
+      }
       combine_waves<Op, SH::WAVES>(wave, lane, wsum, wflag, s_wtot[slot], s_wflag[slot], wpre, wpref, agg, aggf);
 
       // publish, look back, publish the prefix
@@ -1019,8 +1134,23 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
     const carry_t carry = need_carry ? s_carry[slot] : Op::czero();
     const carry_t win = wpref ? wpre : Op::cadd(carry, wpre);
     // a wave without a segment start may add the carry everywhere (no selects)
-    if (SEG && (!Op::kSplitCarry || fh < SH::WSPAN)) apply_carry<Op, SH, SEG, REV>(win, R, lane, fh, a.key);
-    else apply_carry<Op, SH, false, REV>(win, R, lane, fh, a.key);
+    // segmented by subtraction: the plain carry add here, the correction of a
+    // wave that holds a start chunk by chunk as the tile is stored
+    const bool fix = SEG && Op::kInverse && ((head_waves >> wave) & 1u);
+    SegRun<Op> sr{Op::lzero(), Op::narrow(win)};
+    auto store_chunk = [&](const WaveSpan<SH, NT, REV, VEC> &out, const int c) {
+      if constexpr (SEG && Op::kInverse) {
+        if (fix) seg_subtract_chunk<Op, SH, REV>(c, a.exclusive != 0u, wave, lane, s_heads[slot], R[c], sr);
+      }
+      out.store(c, R[c]);
+    };
+    if constexpr (SEG && Op::kInverse) {
+      apply_carry<Op, SH, false, REV>(win, R, lane, fh, a.key);
+    } else if (SEG && (!Op::kSplitCarry || fh < SH::WSPAN)) {
+      apply_carry<Op, SH, SEG, REV>(win, R, lane, fh, a.key);
+    } else {
+      apply_carry<Op, SH, false, REV>(win, R, lane, fh, a.key);
+    }
 
     // Store the tile and load the next one into the same registers: the
     // first half of the stores goes out while the next tile is taken from the
@@ -1030,7 +1160,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
     constexpr int KH = SH::CH / 2;
     const WaveSpan<SH, NT, REV, VEC> out(a.out, a, t, wave, lane);
 #pragma unroll
-    for (int c = 0; c < KH; ++c) out.store(c, R[c]);
+    for (int c = 0; c < KH; ++c) store_chunk(out, c);
     int64_t next = a.stride ? t + a.stride : a.tiles;
     if (resident) {
       if (wave == 0) {
@@ -1045,7 +1175,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
       if constexpr (SEG) heads_map<REV>(a, next, heads_pre);
 #pragma unroll
       for (int c = KH; c < SH::CH; ++c) {
-        out.store(c, R[c]);
+        store_chunk(out, c);
         in.load(c - KH, R[c - KH]);
       }
 #pragma unroll
@@ -1053,7 +1183,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
       if constexpr (SEG) heads_offsets(a, heads_pre);
     } else {
 #pragma unroll
-      for (int c = KH; c < SH::CH; ++c) out.store(c, R[c]);
+      for (int c = KH; c < SH::CH; ++c) store_chunk(out, c);
     }
 
     if (multi && a.ordered) {
