@@ -31,6 +31,32 @@ def test_int_random_offsets_every_config(cfg):
                 assert not msg, "cfg %d n %d S %d ex %d rev %d: %s" % (cfg, n, S, ex, rev, msg)
 
 
+# starts on the boundaries the kernels treat apart -- a lane's 4-group, a
+# 256-element chunk, a wave's span, a tile -- and one element either side;
+# integer sums take the flat scan plus a subtraction per start, so these are
+# the places where a start's prefix is read across lanes, chunks and waves
+@pytest.mark.parametrize("cfg", [0, 1, 5, 7, 20, 21, 22])
+def test_int_starts_on_boundaries(cfg):
+    c = configs()[cfg]
+    tile, wspan = c["tile"], 64 * c["items"]
+    n = 5 * tile + 3 * wspan + 777
+    cuts = set()
+    for unit in (4, 256, wspan, tile):
+        step = max(1, (n // unit) // 9)
+        for m in range(1, n // unit + 1, step):
+            for d in (-1, 0, 1):
+                if 0 < m * unit + d < n:
+                    cuts.add(m * unit + d)
+    off = np.array([0] + sorted(cuts) + [n], dtype=np.int64)
+    a = workloads.full_u32(n, seed=cfg + 7)
+    for ex in (False, True):
+        for rev in (False, True):
+            got = segmented(a, off, exclusive=ex, reverse=rev, cfg=cfg)
+            want = oracle.segmented_int(a, off, exclusive=ex, reverse=rev)
+            msg = first_mismatch(got, want)
+            assert not msg, "cfg %d ex %d rev %d: %s" % (cfg, ex, rev, msg)
+
+
 @pytest.mark.parametrize("cfg", [0, 2, 6, 9])
 def test_f32_segments(cfg):
     g = np.random.default_rng(cfg)
