@@ -119,6 +119,13 @@ def pick(res):
     return best if best_ms < dyn_ms * (1.0 - ORDERED_MARGIN) else dyn_best
 
 
+def merge_keep(entries, dtypes, segmented, lo, hi):
+    """The entries of an existing table that a run tuning the given dtypes,
+    segmented flags and log2 n buckets lo..hi leaves in place."""
+    return [e for e in entries
+            if not (e["op"] in dtypes and e["segmented"] in segmented and lo <= e["log2n"] <= hi)]
+
+
 def main():
     p = argparse.ArgumentParser()
     p.add_argument("--out", default=DEFAULT_OUT)
@@ -128,13 +135,13 @@ def main():
     p.add_argument("--dtypes", default="int,f32")
     p.add_argument("--segmented", default="0,1")
     p.add_argument("--merge", action="store_true",
-                   help="keep the entries of --out for the (dtype, segmented) pairs not tuned now")
+                   help="keep the entries of --out for the buckets not tuned now")
     args = p.parse_args()
     entries = []
-    tuned = {(d, int(s)) for d in args.dtypes.split(",") for s in args.segmented.split(",")}
     if args.merge and os.path.exists(args.out):
         with open(args.out) as f:
-            entries = [e for e in json.load(f)["entries"] if (e["op"], e["segmented"]) not in tuned]
+            entries = merge_keep(json.load(f)["entries"], args.dtypes.split(","),
+                                 [int(s) for s in args.segmented.split(",")], args.min, args.max)
     for dtype in args.dtypes.split(","):
         for seg in [int(s) for s in args.segmented.split(",")]:
             for b in range(args.min, args.max + 1):

@@ -26,3 +26,15 @@ def test_ordered_config_needs_a_clear_win():
     assert pick([(0.900, static), (1.000, counter)]) == static
     # counter modes compete on time alone
     assert pick([(1.000, resident), (0.999, counter)]) == counter
+
+
+def test_merge_replaces_only_the_buckets_tuned():
+    from paper_2312_14874_amd.tune.autotune import merge_keep
+    table = [{"op": op, "segmented": sg, "log2n": b, "config": 0}
+             for op in ("int", "f32") for sg in (0, 1) for b in range(10, 31)]
+    kept = merge_keep(table, ["f32"], [0], 26, 30)
+    gone = [e for e in table if e not in kept]
+    assert len(gone) == 5
+    assert all(e["op"] == "f32" and e["segmented"] == 0 and 26 <= e["log2n"] <= 30 for e in gone)
+    # every bucket of a family tuned in full
+    assert len(merge_keep(table, ["int", "f32"], [1], 10, 30)) == 2 * 21
