@@ -406,8 +406,8 @@ typedef const __attribute__((address_space(4))) int64_t k_i64;
 // so mark_heads does not wait for either at the start of the tile.
 constexpr int kScalarHeads = 8;
 struct HeadsPre {
-  int64_t s_lo, s_hi;
-  int64_t o[kScalarHeads];
+  uint32_t s_lo, s_hi;          // segments s_lo .. s_hi-1 may start in the tile
+  int32_t e[kScalarHeads];      // logical positions of those starts in the tile (-1: none)
 };
 
 template <bool REV>
@@ -418,17 +418,27 @@ __device__ __forceinline__ void heads_map(const KernelArgs &a, int64_t t, HeadsP
     h.s_lo = ((k_u32 *)a.tile_seg)[pt];
     h.s_hi = ((k_u32 *)a.tile_seg)[pt + 1];
   } else {
-    h.s_lo = 0;
-    h.s_hi = a.num_segments + 1;
+    h.s_lo = 0u;
+    h.s_hi = (uint32_t)a.num_segments + 1u;
   }
 }
 
-__device__ __forceinline__ void heads_offsets(const KernelArgs &a, HeadsPre &h) {
-  const int64_t cnt = h.s_hi - h.s_lo;
+template <int TILE, bool REV>
+__device__ __forceinline__ void heads_offsets(const KernelArgs &a, int64_t t, HeadsPre &h) {
+  const int64_t cnt = (int64_t)h.s_hi - (int64_t)h.s_lo;
   if (a.tile_seg && cnt > 0 && cnt <= kScalarHeads) {
+    const int pt = __builtin_amdgcn_readfirstlane((int)(REV ? (a.tiles - 1 - t) : t));
+    const int64_t pb = (int64_t)pt * TILE;
+    const int64_t rem = a.n - pb;
+    const int valid = rem < TILE ? (int)rem : TILE;
     // indices clamped into [s_lo, s_hi - 1] so every load stays inside offsets[0..S]
 #pragma unroll
-    for (int k = 0; k < kScalarHeads; ++k) h.o[k] = ((k_i64 *)a.offsets)[h.s_lo + (k < cnt ? k : cnt - 1)];
+    for (int k = 0; k < kScalarHeads; ++k) {
+      const int64_t s = (int64_t)h.s_lo + (k < cnt ? k : cnt - 1);
+      const int64_t ph = ((k_i64 *)a.offsets)[s] - (REV ? 1 : 0);   // physical first element (last for reverse)
+      const bool in = k < cnt && (REV ? (s >= 1) : (s < a.num_segments)) && ph >= pb && ph < pb + valid;
+      h.e[k] = in ? (REV ? (TILE - 1 - (int)(ph - pb)) : (int)(ph - pb)) : -1;
+    }
   }
 }
 
@@ -436,43 +446,30 @@ template <int BLOCK, int TILE, int WSPAN, bool REV>
 __device__ uint32_t mark_heads(const KernelArgs &a, int64_t t, const HeadsPre &h, uint32_t *heads,
                                uint32_t *flag) {
   const int tid = threadIdx.x;
-  const int pt = __builtin_amdgcn_readfirstlane((int)(REV ? (a.tiles - 1 - t) : t));
-  const int64_t pb = (int64_t)pt * TILE;
-  const int64_t rem = a.n - pb;
-  const int valid = rem < TILE ? (int)rem : TILE;
-  const int shift = REV ? 1 : 0;
   const int64_t s_lo = h.s_lo, s_hi = h.s_hi;
   if (s_hi <= s_lo) return 0u;
   const int64_t cnt = s_hi - s_lo;
   if (a.tile_seg && cnt <= kScalarHeads) {
-    const int64_t(&o)[kScalarHeads] = h.o;
     uint32_t waves = 0u;
 #pragma unroll
-    for (int k = 0; k < kScalarHeads; ++k) {
-      const int64_t s = s_lo + k;
-      const int64_t ph = o[k] - shift;
-      if (k < cnt && (REV ? (s >= 1) : (s < a.num_segments)) && ph >= pb && ph < pb + valid) {
-        const int e = REV ? (TILE - 1 - (int)(ph - pb)) : (int)(ph - pb);
-        waves |= 1u << (e / WSPAN);
-      }
-    }
+    for (int k = 0; k < kScalarHeads; ++k)
+      if (h.e[k] >= 0) waves |= 1u << (h.e[k] / WSPAN);
     if (!waves) return 0u;
     for (int i = tid; i < TILE / 32; i += BLOCK) heads[i] = 0u;
     __syncthreads();
     if (tid == 0) {
 #pragma unroll
-      for (int k = 0; k < kScalarHeads; ++k) {
-        const int64_t s = s_lo + k;
-        const int64_t ph = o[k] - shift;
-        if (k < cnt && (REV ? (s >= 1) : (s < a.num_segments)) && ph >= pb && ph < pb + valid) {
-          const int e = REV ? (TILE - 1 - (int)(ph - pb)) : (int)(ph - pb);
-          atomicOr(&heads[e >> 5], 1u << (e & 31));
-        }
-      }
+      for (int k = 0; k < kScalarHeads; ++k)
+        if (h.e[k] >= 0) atomicOr(&heads[h.e[k] >> 5], 1u << (h.e[k] & 31));
     }
     __syncthreads();
     return waves;
   }
+  const int pt = __builtin_amdgcn_readfirstlane((int)(REV ? (a.tiles - 1 - t) : t));
+  const int64_t pb = (int64_t)pt * TILE;
+  const int64_t rem = a.n - pb;
+  const int valid = rem < TILE ? (int)rem : TILE;
+  const int shift = REV ? 1 : 0;
   for (int i = tid; i < TILE / 32; i += BLOCK) heads[i] = 0u;
   if (tid == 0) *flag = 0u;
   __syncthreads();
@@ -778,32 +775,43 @@ __device__ __forceinline__ void seg_subtract_chunk(int c, bool ex, int wave, int
   constexpr int ph[4] = {p0, p1, p2, p3};
   const uint32_t *hw = heads + ((wave * SH::WSPAN + lane * 4) >> 5);
   const uint32_t hb = (hw[c * 8] >> ((lane * 4) & 31)) & 0xfu;   // bit k: a start at logical element k
-  lane_t v[4];
+  uint64_t hm = ballot(hb != 0u);                                  // lanes of the chunk with a start
+  const uint32_t last = readlane32(r[p3], 63);
+  if (hm == 0ull) {
+    // no start in the chunk: every element takes away the latest S
 #pragma unroll
-  for (int k = 0; k < 4; ++k) v[k] = Op::lfrom(r[ph[k]]);
-  // S at a start at k, and the S of the lane's latest start at or before k
-  const lane_t up = Op::lfrom(lane_up1(Op::lbits(v[3])));
-  lane_t ls[4];
+    for (int k = 0; k < 4; ++k) r[ph[k]] = Op::lbits(Op::lsub(Op::lfrom(r[ph[k]]), sr.run));
+  } else {
+    // the starts in logical order (lanes up, then elements within the lane);
+    // each one's S replaces the latest S from its position on
+    uint32_t sub[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const lane_t before = k > 0 ? v[k > 0 ? k - 1 : 0] : (lane == 0 ? sr.prev_last : up);
-    const lane_t sk = ex ? v[k] : before;
-    ls[k] = ((hb >> k) & 1u) ? sk : (k > 0 ? ls[k > 0 ? k - 1 : 0] : Op::lzero());
+    for (int k = 0; k < 4; ++k) sub[k] = Op::lbits(sr.run);
+    lane_t cur = sr.run;
+    while (hm) {
+      const int l = __builtin_ctzll(hm);
+      hm &= hm - 1ull;
+      const uint32_t bits = __builtin_amdgcn_readlane(hb, l);
+      const bool gt = lane > l, ge = lane >= l;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if ((bits >> k) & 1u) {
+          // exclusive: the value at the start; inclusive: the value before it
+          uint32_t sv;
+          if (ex) sv = readlane32(r[ph[k]], l);
+          else if (k > 0) sv = readlane32(r[ph[k > 0 ? k - 1 : 0]], l);
+          else sv = l > 0 ? readlane32(r[p3], l - 1) : Op::lbits(sr.prev_last);
+          cur = Op::lfrom(sv);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) sub[j] = (j >= k ? ge : gt) ? sv : sub[j];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[ph[k]] = Op::lbits(Op::lsub(Op::lfrom(r[ph[k]]), Op::lfrom(sub[k])));
+    sr.run = cur;
   }
-  // lanes with a start carry the S of their latest one; the segmented scan
-  // gives each lane the S of the latest start in lanes <= l (f: any)
-  lane_t x = hb ? ls[3] : Op::lzero();
-  uint32_t f = hb != 0u;
-  wave_scan_seg<Op>(x, f);
-  const lane_t xin = Op::lfrom(lane_up1(Op::lbits(x)));
-  const lane_t incoming = lane_up1(f) ? xin : sr.run;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const lane_t sub = (hb & ((2u << k) - 1u)) ? ls[k] : incoming;
-    r[ph[k]] = Op::lbits(Op::lsub(v[k], sub));
-  }
-  if (readlane32(f, 63)) sr.run = Op::lfrom(readlane32(Op::lbits(x), 63));
-  sr.prev_last = Op::lfrom(readlane32(Op::lbits(v[3]), 63));
+  sr.prev_last = Op::lfrom(last);
 }
 
 // The plain wave-local prefix before the wave's last segment start (the
@@ -812,7 +820,6 @@ __device__ __forceinline__ void seg_subtract_chunk(int c, bool ex, int wave, int
 template <class Op, class SH, bool REV>
 __device__ __forceinline__ typename Op::lane_t seg_last_prefix(bool ex, int wave, int lane, const uint32_t *heads,
                                                                const u32x4 (&R)[SH::CH]) {
-  using lane_t = typename Op::lane_t;
   constexpr int p0 = REV ? 3 : 0, p1 = REV ? 2 : 1, p2 = REV ? 1 : 2, p3 = REV ? 0 : 3;
   constexpr int ph[4] = {p0, p1, p2, p3};
   const uint32_t *hw = heads + ((wave * SH::WSPAN + lane * 4) >> 5);
@@ -1041,7 +1048,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
   if constexpr (SEG) {
     if (t < a.tiles) {
       heads_map<REV>(a, t, heads_pre);
-      heads_offsets(a, heads_pre);
+      heads_offsets<SH::TILE, REV>(a, t, heads_pre);
     }
   }
 
@@ -1180,7 +1187,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
       }
 #pragma unroll
       for (int c = SH::CH - KH; c < SH::CH; ++c) in.load(c, R[c]);
-      if constexpr (SEG) heads_offsets(a, heads_pre);
+      if constexpr (SEG) heads_offsets<SH::TILE, REV>(a, next, heads_pre);
     } else {
 #pragma unroll
       for (int c = KH; c < SH::CH; ++c) store_chunk(out, c);
