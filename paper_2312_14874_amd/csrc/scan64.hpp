@@ -114,19 +114,37 @@ __device__ __forceinline__ int64_t acquire_tile64(const KernelArgs &a, uint32_t 
   return (int64_t)tk;
 }
 
+// The status pair of window lane `lane` (tile base - lane), or an empty
+// PREFIX before tile 0.
+__device__ __forceinline__ void lb_pair64(const uint64_t *st, int64_t base, int lane, uint64_t &lo, uint64_t &hi) {
+  const int64_t idx = base - lane;
+  lo = ((uint64_t)kPrefix << 32);
+  hi = ((uint64_t)kPrefix << 32);
+  if (idx >= 0) {
+    lo = ld_agent(st + 2 * idx);
+    hi = ld_agent(st + 2 * idx + 1);
+  }
+}
+
 // Carry into tile t (one wave): sum of the aggregates back to the nearest
-// PREFIX, read 64 tiles per poll (lane l: tile t-1-l of the window).
-template <class Op>
-__device__ uint64_t look_back64(const uint64_t *st, int64_t t, uint32_t spin_limit, uint32_t *err) {
+// PREFIX, read 64 tiles per poll (lane l: tile t-1-l of the window).  With
+// PRE the first poll's pair (lo0, hi0) was loaded by the caller, so its round
+// trip overlaps the caller's work.
+template <class Op, bool PRE = false>
+__device__ uint64_t look_back64(const uint64_t *st, int64_t t, uint32_t spin_limit, uint32_t *err,
+                                uint64_t lo0 = 0, uint64_t hi0 = 0) {
   const int lane = (int)(opaque_tid() & 63u);
   uint64_t acc = 0;
   int64_t base = t - 1;
+  bool pre = PRE;
   for (uint32_t spins = 0;;) {
-    const int64_t idx = base - lane;
-    uint64_t lo = ((uint64_t)kPrefix << 32), hi = ((uint64_t)kPrefix << 32);   // before tile 0: empty PREFIX
-    if (idx >= 0) {
-      lo = ld_agent(st + 2 * idx);
-      hi = ld_agent(st + 2 * idx + 1);
+    uint64_t lo, hi;
+    if (pre) {
+      lo = lo0;
+      hi = hi0;
+      pre = false;
+    } else {
+      lb_pair64(st, base, lane, lo, hi);
     }
     const uint32_t flo = (uint32_t)(lo >> 32), fhi = (uint32_t)(hi >> 32);
     const uint32_t f = flo == fhi ? flo : kEmpty;
@@ -179,7 +197,10 @@ __device__ __forceinline__ uint64_t u64_of(uint32_t lo, uint32_t hi) { return ((
 
 // Resident grid, tiles from the device counter; ITEMS elements per thread
 // (2 per chunk and lane), the wave's span WSPAN = 64 * ITEMS elements.
-template <class Op, int BLOCK, int ITEMS, int MINW, bool REV>
+// EARLY: the tile's aggregate is summed from the lanes' element pairs and
+// published before the in-register scan, and wave 0 issues the first
+// look-back poll then, so that its round trip overlaps the scan.
+template <class Op, int BLOCK, int ITEMS, int MINW, bool REV, bool EARLY = false>
 __global__ void __launch_bounds__(BLOCK, MINW) scan64_tiles(KernelArgs a) {
   static_assert(ITEMS % 2 == 0, "two elements per 16-byte group");
   constexpr int WAVES = BLOCK / 64;
@@ -227,10 +248,39 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan64_tiles(KernelArgs a) {
     for (int c = 0; c < CH; ++c) in.load(c, R[c]);
   }
   while (t < a.tiles) {
+    uint64_t wpre = 0, agg = 0;
+    uint64_t wlo = 0, whi = 0;   // EARLY: wave 0's first look-back poll
+    if constexpr (EARLY) {
+      // lane totals of the loaded pairs, the wave totals, the tile aggregate
+      uint64_t lt = 0;
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const uint64_t p = Op::add(u64_of(R[c][E0], R[c][E0 + 1]), u64_of(R[c][E1], R[c][E1 + 1]));
+        lt = c > 0 ? Op::add(lt, p) : p;
+      }
+      const uint64_t wt = readlane64(Op::wave_scan(lt), 63);
+      if (lane == 0) s_wtot[wave] = wt;
+      __syncthreads();
+#pragma unroll
+      for (int w = 0; w < WAVES; ++w) {
+        if (w == wave) wpre = agg;
+        agg = w > 0 ? Op::add(agg, s_wtot[w]) : s_wtot[w];
+      }
+      // the wave's prefix now, in one register pair (not the fold's partial
+      // sums kept until the carry is added)
+      asm volatile("" : "+v"(wpre));
+      if (multi && wave == 0) {
+        uint64_t *st = a.status + parity * a.capacity;
+        if (lane == 0) publish64(st, t, agg, t == 0 ? kPrefix : kAgg);
+        if (t > 0) lb_pair64(st, t - 1, lane, wlo, whi);
+      }
+    }
     // in-register scan: per chunk the lane's two elements, then the lanes
     uint64_t wsum = 0;
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
+      // the pair sums are computed again, not kept from the aggregate's loop
+      if constexpr (EARLY) asm volatile("" : "+v"(R[c]));
       const uint64_t x0 = u64_of(R[c][E0], R[c][E0 + 1]);
       const uint64_t x1 = Op::add(u64_of(R[c][E1], R[c][E1 + 1]), x0);
       const uint64_t x = Op::wave_scan(x1);
@@ -245,16 +295,27 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan64_tiles(KernelArgs a) {
       wsum = c > 0 ? Op::add(wsum, readlane64(x, 63)) : readlane64(x, 63);
       asm volatile("" : "+v"(R[c]));
     }
-    // wave totals: this wave's prefix and the tile's aggregate, left to right
-    if (lane == 0) s_wtot[wave] = wsum;
-    __syncthreads();
-    uint64_t wpre = 0, agg = 0;
+    if constexpr (EARLY) {
+      if (multi && wave == 0) {
+        uint64_t *st = a.status + parity * a.capacity;
+        uint64_t carry = 0;
+        if (t > 0) {
+          carry = look_back64<Op, true>(st, t, a.spin_limit, a.err, wlo, whi);
+          if (lane == 0) publish64(st, t, Op::add(carry, agg), kPrefix);
+        }
+        if (lane == 0) s_carry = carry;
+      }
+    } else {
+      // wave totals: this wave's prefix and the tile's aggregate, left to right
+      if (lane == 0) s_wtot[wave] = wsum;
+      __syncthreads();
 #pragma unroll
-    for (int w = 0; w < WAVES; ++w) {
-      if (w == wave) wpre = agg;
-      agg = w > 0 ? Op::add(agg, s_wtot[w]) : s_wtot[w];
+      for (int w = 0; w < WAVES; ++w) {
+        if (w == wave) wpre = agg;
+        agg = w > 0 ? Op::add(agg, s_wtot[w]) : s_wtot[w];
+      }
     }
-    if (multi && wave == 0) {
+    if (!EARLY && multi && wave == 0) {
       uint64_t *st = a.status + parity * a.capacity;
       uint64_t carry = 0;
       if (t == 0) {
