@@ -195,6 +195,12 @@ struct WaveSpan64 {
 
 __device__ __forceinline__ uint64_t u64_of(uint32_t lo, uint32_t hi) { return ((uint64_t)hi << 32) | lo; }
 
+// A wave-uniform 64-bit value in scalar registers.
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+  return u64_of((uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x),
+                (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32)));
+}
+
 // Resident grid, tiles from the device counter; ITEMS elements per thread
 // (2 per chunk and lane), the wave's span WSPAN = 64 * ITEMS elements.
 // EARLY: the tile's aggregate is summed from the lanes' element pairs and
@@ -239,7 +245,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan64_tiles(KernelArgs a) {
     }
     __syncthreads();
     parity = s_parity;
-    t = s_tile;
+    t = (int64_t)uniform64((uint64_t)s_tile);
   }
   u32x4 R[CH];
   if (t < a.tiles) {
@@ -266,9 +272,10 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan64_tiles(KernelArgs a) {
         if (w == wave) wpre = agg;
         agg = w > 0 ? Op::add(agg, s_wtot[w]) : s_wtot[w];
       }
-      // the wave's prefix now, in one register pair (not the fold's partial
-      // sums kept until the carry is added)
-      asm volatile("" : "+v"(wpre));
+      // the wave's prefix and the aggregate now, in scalar registers (not
+      // the fold's partial sums kept until the carry is added)
+      wpre = uniform64(wpre);
+      agg = uniform64(agg);
       if (multi && wave == 0) {
         uint64_t *st = a.status + parity * a.capacity;
         if (lane == 0) publish64(st, t, agg, t == 0 ? kPrefix : kAgg);
@@ -350,7 +357,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan64_tiles(KernelArgs a) {
         if (lane == 0) s_tile = tk;
       }
       __syncthreads();
-      next = s_tile;
+      next = (int64_t)uniform64((uint64_t)s_tile);
     }
     if (next < a.tiles) {
       const Span in(a.in, a.n, span_base(next));
