@@ -83,6 +83,23 @@ def test_flat(dtype, op, cfg):
             assert not first_mismatch(got, want), (op, np.dtype(dtype).name, cfg, ex, "reverse")
 
 
+# xor takes the integer sum's correction per segment start (it is its own
+# inverse): runs of segments of length 1-4 put several starts in one lane
+@pytest.mark.parametrize("cfg", [None, 5, 21])
+def test_segmented_xor_dense_starts(cfg):
+    g = np.random.default_rng(3300 + (cfg or 0))
+    lens = g.integers(1, 5, size=4000)
+    lens[100:110] = 30000                            # long segments between the clusters
+    lens[2000:2005] = 70000
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    a = walk(int(off[-1]), 3301, np.uint32)
+    for ex in (False, True):
+        for rev in (False, True):
+            want = oracle.segmented_op(a, off, "xor", exclusive=ex, reverse=rev)
+            got = run_seg(a, off, "xor", exclusive=ex, reverse=rev, cfg=cfg)
+            assert not first_mismatch(got, want), (cfg, ex, rev)
+
+
 @pytest.mark.parametrize("op", ["max", "min", "xor"])
 @pytest.mark.parametrize("n", [1, 5, 4096, 65537, 1 << 20])
 def test_sizes_misaligned_inplace(op, n):

@@ -57,6 +57,34 @@ def test_int_starts_on_boundaries(cfg):
             assert not msg, "cfg %d ex %d rev %d: %s" % (cfg, ex, rev, msg)
 
 
+# clusters of very short segments (lengths 1-4, so a lane's 4-group and a
+# 256-element chunk hold several starts, some in the same lane) between long
+# ones: the integer correction walks every start of a chunk in order
+@pytest.mark.parametrize("cfg", [0, 1, 2, 5, 20, 21, 22])
+def test_int_dense_start_clusters(cfg):
+    c = configs()[cfg]
+    tile, wspan = c["tile"], 64 * c["items"]
+    n = 3 * tile + 2 * wspan + 1234
+    g = np.random.default_rng(500 + cfg)
+    cuts = set()
+    centres = [wspan - 3, wspan + 250, tile - 1, tile + wspan // 2, 2 * tile + 256 * 5 - 2, n - 60]
+    centres += list(g.integers(1, n - 1, size=4))
+    for c0 in centres:
+        x = int(c0)
+        for _ in range(40):
+            if 0 < x < n:
+                cuts.add(x)
+            x += int(g.integers(1, 5))
+    off = np.array([0] + sorted(cuts) + [n], dtype=np.int64)
+    a = workloads.full_u32(n, seed=cfg + 11)
+    for ex in (False, True):
+        for rev in (False, True):
+            got = segmented(a, off, exclusive=ex, reverse=rev, cfg=cfg)
+            want = oracle.segmented_int(a, off, exclusive=ex, reverse=rev)
+            msg = first_mismatch(got, want)
+            assert not msg, "cfg %d ex %d rev %d: %s" % (cfg, ex, rev, msg)
+
+
 @pytest.mark.parametrize("cfg", [0, 2, 6, 9])
 def test_f32_segments(cfg):
     g = np.random.default_rng(cfg)
