@@ -251,20 +251,32 @@ __device__ __forceinline__ void lb_window(const uint64_t *st, int32_t base, uint
 // What one examined window decided.
 enum LbStep { kLbDone = 0, kLbWait = 1, kLbMove = 2 };
 
-// Examine window w of base `base`: kLbDone with the carry in `out`, kLbWait
+// The look-back's state between polls: the window base (the tile of lane 0's
+// word), the sum of the aggregates passed so far, the carry once found, and
+// what the last examined window decided.  Passed and returned by value, so
+// that it stays in registers (through references the compiler kept the base
+// and the running sum in private memory, a round trip per poll).
+template <class Op>
+struct LbState {
+  int32_t base;
+  typename Op::carry_t acc;
+  typename Op::carry_t out;
+  int r;
+};
+
+// Examine window w of base s.base: kLbDone with the carry in out, kLbWait
 // (a needed word is still EMPTY, or a float window holds no PREFIX yet), or
 // kLbMove (integers: a full window of aggregates was added to acc and base
 // moved back past it).
 template <class Op, int KW>
-__device__ __forceinline__ int lb_examine(uint64_t (&w)[KW], int32_t &base, typename Op::carry_t &acc,
-                                          typename Op::carry_t &out) {
+__device__ __forceinline__ LbState<Op> lb_examine(uint64_t (&w)[KW], LbState<Op> s) {
   using carry_t = typename Op::carry_t;
   const int lane = (int)(opaque_tid() & 63u);
   constexpr int kNone = 1 << 30;
   // predecessors before tile 0: an empty prefix
 #pragma unroll
   for (int k = 0; k < KW; ++k)
-    if (base - (64 * k + lane) < 0) w[k] = Op::pack(Op::czero(), kPrefix);
+    if (s.base - (64 * k + lane) < 0) w[k] = Op::pack(Op::czero(), kPrefix);
   int dP = kNone, dE = kNone;
 #pragma unroll
   for (int k = 0; k < KW; ++k) {
@@ -274,7 +286,8 @@ __device__ __forceinline__ int lb_examine(uint64_t (&w)[KW], int32_t &base, type
     if (dP == kNone && bP) dP = 64 * k + __builtin_ctzll(bP);
     if (dE == kNone && bE) dE = 64 * k + __builtin_ctzll(bE);
   }
-  if (dE < dP) return kLbWait;
+  s.r = kLbWait;
+  if (dE < dP) return s;
   if (dP == kNone) {
     if constexpr (Op::kExact) {
       // a full window of aggregates: add them all and move further back
@@ -282,12 +295,11 @@ __device__ __forceinline__ int lb_examine(uint64_t (&w)[KW], int32_t &base, type
 #pragma unroll
       for (int k = 0; k < KW; ++k) part = Op::cadd(part, Op::value_of(w[k]));
       part = Op::narrow(readlane32(Op::lbits(wave_scan<Op>(part)), 63));
-      acc = Op::cadd(acc, part);
-      base -= 64 * KW;
-      return kLbMove;
-    } else {
-      return kLbWait;
+      s.acc = Op::cadd(s.acc, part);
+      s.base -= 64 * KW;
+      s.r = kLbMove;
     }
+    return s;
   }
   if constexpr (Op::kExact) {
     carry_t part = Op::czero();
@@ -295,7 +307,7 @@ __device__ __forceinline__ int lb_examine(uint64_t (&w)[KW], int32_t &base, type
     for (int k = 0; k < KW; ++k)
       if (64 * k + lane <= dP) part = Op::cadd(part, Op::value_of(w[k]));
     part = Op::narrow(readlane32(Op::lbits(wave_scan<Op>(part)), 63));
-    out = Op::cadd(acc, part);
+    s.out = Op::cadd(s.acc, part);
   } else {
     // left fold from the PREFIX at distance dP down to distance 0; the
     // window index k is kept static so no private array is indexed
@@ -310,9 +322,10 @@ __device__ __forceinline__ int lb_examine(uint64_t (&w)[KW], int32_t &base, type
       if (l > 63) l = 63;
       for (; l >= 0; --l) c = Op::canon(Op::cadd(c, Op::value_of(readlane64(w[k], l))));
     }
-    out = c;
+    s.out = c;
   }
-  return kLbDone;
+  s.r = kLbDone;
+  return s;
 }
 
 // Exclusive carry into tile t (t >= 1), starting from an already issued
@@ -320,24 +333,22 @@ __device__ __forceinline__ int lb_examine(uint64_t (&w)[KW], int32_t &base, type
 template <class Op, int K1, int K>
 __device__ typename Op::carry_t look_back(const uint64_t *st, int64_t t, uint32_t spin_limit,
                                           uint32_t *err, uint64_t (&w1)[K1]) {
-  using carry_t = typename Op::carry_t;
-  carry_t acc = Op::czero(), out = Op::czero();
-  int32_t base = (int32_t)t - 1;
-  int r = lb_examine<Op, K1>(w1, base, acc, out);
+  LbState<Op> s{(int32_t)t - 1, Op::czero(), Op::czero(), kLbWait};
+  s = lb_examine<Op, K1>(w1, s);
   uint32_t spins = 0;
-  while (r != kLbDone) {
-    if (r == kLbWait) {
+  while (s.r != kLbDone) {
+    if (s.r == kLbWait) {
       if (++spins > spin_limit) {
         if ((opaque_tid() & 63u) == 0) raise_error(err);
-        return acc;
+        return s.acc;
       }
       __builtin_amdgcn_s_sleep(1);
     }
     uint64_t w[K];
-    lb_window<Op, K>(st, base, w);
-    r = lb_examine<Op, K>(w, base, acc, out);
+    lb_window<Op, K>(st, s.base, w);
+    s = lb_examine<Op, K>(w, s);
   }
-  return out;
+  return s.out;
 }
 
 // Tile addressing.  Logical element e of a tile is physical pb+e going
