@@ -1006,6 +1006,10 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
   constexpr int K = 4;   // look-back window = 64*K tiles per poll
   constexpr int K1 = 1;  // EARLY: first poll, issued before the scan
   constexpr bool kEarly = EARLY && !SEG;
+  // segmented, operators with an inverse: a tile without a segment start
+  // publishes its aggregate before the scan, as kEarly does (forward scans:
+  // the reverse variant's registers do not fit it)
+  constexpr bool kSegEarly = EARLY && SEG && Op::kInverse && !REV;
   using carry_t = typename Op::carry_t;
 
   __shared__ carry_t s_wtot[2][SH::WAVES];
@@ -1018,6 +1022,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
   // tile: a wave may still read the last tile's bits while it stores (the
   // subtraction of segmented scans) when another wave marks the next tile's
   __shared__ uint32_t s_heads[2][SEG ? SH::TILE / 32 : 1];
+  __shared__ carry_t s_etot[kSegEarly ? SH::WAVES : 1];   // wave totals of kSegEarly
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -1115,6 +1120,32 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
         if (lane == 0) s_carry[slot] = carry;
       }
     } else {
+      // kSegEarly, a tile without a segment start: the lanes' sums of the
+      // loaded values (R is only read), the wave totals and the aggregate,
+      // published with the first poll issued before the scan
+      bool seg_early = false;
+      uint64_t w1s[K1];
+      if constexpr (kSegEarly) {
+        seg_early = head_waves == 0u && need_carry && multi;
+        if (seg_early) {
+          typename Op::lane_t ls = Op::lzero();
+#pragma unroll
+          for (int c = 0; c < SH::CH; ++c)
+            ls = Op::ladd(ls, Op::ladd(Op::ladd(Op::lfrom(R[c][0]), Op::lfrom(R[c][1])),
+                                       Op::ladd(Op::lfrom(R[c][2]), Op::lfrom(R[c][3]))));
+          const carry_t wt = wave_total<Op>(Op::widen(ls));
+          if (lane == 0) s_etot[wave] = wt;
+          __syncthreads();
+          carry_t ea = Op::czero();
+#pragma unroll
+          for (int w = 0; w < SH::WAVES; ++w) ea = Op::cadd(ea, s_etot[w]);
+          if (wave == 0) {
+            uint64_t *st = a.status + parity * a.capacity;
+            publish_first<Op>(st, t, ea, 0u);
+            lb_window<Op, K1>(st, (int32_t)t - 1, w1s);
+          }
+        }
+      }
       if constexpr (SEG && Op::kInverse) {
         // the flat scan's code for every wave; a wave that holds a segment
         // start contributes its total since the last one (the elements are
@@ -1133,15 +1164,19 @@ __global__ void __launch_bounds__(BLOCK, MINW) scan_tiles(KernelArgs a) {
       // publish, look back, publish the prefix
       if (multi && wave == 0) {
         uint64_t *st = a.status + parity * a.capacity;
-        publish_first<Op>(st, t, agg, aggf);
+        if (!seg_early) publish_first<Op>(st, t, agg, aggf);
         if (a.ordered && lane == 0 && t != a.tiles - 1)
           (void)__hip_atomic_fetch_add(a.pubcnt + (parity * kPubSlots + (t % kPubSlots)) * kPubStride, 1ull,
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         carry_t carry = Op::czero();
         if (need_carry) {
-          uint64_t w[K];
-          lb_window<Op, K>(st, (int32_t)t - 1, w);
-          carry = look_back<Op, K, K>(st, t, a.spin_limit, a.err, w);
+          if (seg_early) {
+            carry = look_back<Op, K1, K>(st, t, a.spin_limit, a.err, w1s);
+          } else {
+            uint64_t w[K];
+            lb_window<Op, K>(st, (int32_t)t - 1, w);
+            carry = look_back<Op, K, K>(st, t, a.spin_limit, a.err, w);
+          }
           if (!aggf && lane == 0)
             st_agent(st + t, Op::pack(Op::canon(Op::cadd(carry, Op::canon(agg))), kPrefix));
         }

@@ -18,7 +18,7 @@ namespace mi355scan {
 #define MI355SCAN_FNS(B, I, NT, VEC, WUF, WFF, WUS, WFS, E)                                   \
   {{{(const void *)&scan_tiles<OpsU32, B, I, false, (NT != 0), false, VEC, WUF, E>,            \
      (const void *)&scan_tiles<OpsU32, B, I, false, (NT != 0), true, VEC, WUF, E>},            \
-    {(const void *)&scan_tiles<OpsU32, B, I, true, (NT != 0), false, VEC, WUS>,                \
+    {(const void *)&scan_tiles<OpsU32, B, I, true, (NT != 0), false, VEC, WUS, E>,             \
      (const void *)&scan_tiles<OpsU32, B, I, true, (NT != 0), true, VEC, WUS>}},               \
    {{(const void *)&scan_tiles<OpsF32, B, I, false, (NT != 0), false, VEC, WFF, E>,            \
      (const void *)&scan_tiles<OpsF32, B, I, false, (NT != 0), true, VEC, WFF, E>},            \
@@ -30,7 +30,7 @@ namespace mi355scan {
      (const void *)&scan_tiles<OpsMaxU32, B, I, true, (NT != 0), true, VEC, WUS>}},            \
    {{(const void *)&scan_tiles<OpsXorU32, B, I, false, (NT != 0), false, VEC, WUF, E>,         \
      (const void *)&scan_tiles<OpsXorU32, B, I, false, (NT != 0), true, VEC, WUF, E>},         \
-    {(const void *)&scan_tiles<OpsXorU32, B, I, true, (NT != 0), false, VEC, WUS>,             \
+    {(const void *)&scan_tiles<OpsXorU32, B, I, true, (NT != 0), false, VEC, WUS, E>,          \
      (const void *)&scan_tiles<OpsXorU32, B, I, true, (NT != 0), true, VEC, WUS>}}}
 
 // {block, items, nontemporal, waves per SIMD: u32 flat, f32 flat, u32 segmented, f32 segmented}
@@ -48,11 +48,13 @@ const KernelShape kShapes[] = {
     MI355SCAN_TILES(512, 128, 1, 2, 2, 2, 2, false),     // 6
     MI355SCAN_TILES(1024, 64, 1, 4, 4, 4, 4, false),     // 7
     MI355SCAN_TILES(768, 128, 1, 3, 3, 3, 3, false),     // 8
-    // flat scans publish the tile aggregate before the in-register scan
-    // (EARLY); segmented entries as the shapes above
+    // the tile aggregate is published before the in-register scan (EARLY):
+    // flat scans, and forward integer-sum and xor segmented scans in tiles
+    // without a segment start; other segmented entries as the shapes above
     MI355SCAN_TILES(512, 128, 1, 2, 2, 2, 2, true),      // 9
     MI355SCAN_TILES(256, 128, 1, 2, 2, 2, 2, true),      // 10
     MI355SCAN_TILES(256, 64, 1, 3, 3, 3, 3, true),       // 11
+    MI355SCAN_TILES(1024, 64, 1, 4, 4, 4, 4, true),      // 12
 };
 const int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
@@ -75,6 +77,7 @@ const Config kConfigs[] = {
     {8, 1, 1, 75}, {8, 1, 1, 88}, {6, 1, 1, 75},      // 27-29 one per CU on part of the CUs
     {9, 1, 1, 100}, {10, 1, 1, 100}, {11, 1, 1, 100},   // 30-32 early publication, one per CU
     {10, 1, 2, 100}, {11, 1, 2, 100},                    // 33-34 early publication, two per CU
+    {12, 1, 1, 100},                                     // 35    early publication, sixteen waves per CU
 };
 const int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 

@@ -85,7 +85,7 @@ def test_flat(dtype, op, cfg):
 
 # xor takes the integer sum's correction per segment start (it is its own
 # inverse): runs of segments of length 1-4 put several starts in one lane
-@pytest.mark.parametrize("cfg", [None, 5, 21])
+@pytest.mark.parametrize("cfg", [None, 5, 21, 35])
 def test_segmented_xor_dense_starts(cfg):
     g = np.random.default_rng(3300 + (cfg or 0))
     lens = g.integers(1, 5, size=4000)

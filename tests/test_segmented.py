@@ -35,7 +35,7 @@ def test_int_random_offsets_every_config(cfg):
 # 256-element chunk, a wave's span, a tile -- and one element either side;
 # integer sums take the flat scan plus a subtraction per start, so these are
 # the places where a start's prefix is read across lanes, chunks and waves
-@pytest.mark.parametrize("cfg", [0, 1, 5, 7, 20, 21, 22])
+@pytest.mark.parametrize("cfg", [0, 1, 5, 7, 20, 21, 22, 30, 35])
 def test_int_starts_on_boundaries(cfg):
     c = configs()[cfg]
     tile, wspan = c["tile"], 64 * c["items"]
@@ -60,7 +60,7 @@ def test_int_starts_on_boundaries(cfg):
 # clusters of very short segments (lengths 1-4, so a lane's 4-group and a
 # 256-element chunk hold several starts, some in the same lane) between long
 # ones: the integer correction walks every start of a chunk in order
-@pytest.mark.parametrize("cfg", [0, 1, 2, 5, 20, 21, 22])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 5, 20, 21, 22, 30, 35])
 def test_int_dense_start_clusters(cfg):
     c = configs()[cfg]
     tile, wspan = c["tile"], 64 * c["items"]
