@@ -765,10 +765,12 @@ __device__ __forceinline__ void scan_wave(uint32_t exclusive, uint32_t key, int 
 // takes away S_h, the carried plain prefix of the elements before h
 // (exclusive: the value at h; inclusive: the value just before h, which for
 // h = 0 is the carry into the wave), which leaves the scan of its segment;
-// elements before the first start keep the carry.  Per chunk the lane finds
-// the S of its latest start at or before each element, a segmented lane scan
-// brings the latest start's S of earlier lanes, and each chunk passes the
-// latest S on to the next (SegRun, wave-uniform).  It runs chunk by chunk as
+// elements before the first start keep the carry.  Per chunk: without a
+// start in the chunk every element takes away the latest S; otherwise the
+// wave walks the chunk's starts in logical order (lanes up, then elements in
+// the lane) with uniform reads, and each start's S replaces the latest one
+// from its position on; the latest S passes to the next chunk (SegRun,
+// wave-uniform).  It runs chunk by chunk as
 // the tile is stored, so that only the chunk being stored passes through the
 // branch: a branch over every register of the tile (the segmented carry add
 // beside the plain one, or this correction as one pass) makes the
