@@ -40,10 +40,13 @@ constexpr uint32_t never_kept() {
 //  - count: each lane counts its kept elements per chunk, three chunks to a
 //    word (10 bits each: a chunk keeps at most 256), so one wave scan of a
 //    word gives every lane its offset in three chunks and the chunks' totals;
-//  - pack and write, after the look-back: per chunk, the wave packs its kept
-//    elements into its own LDS row (every element is written somewhere, so
-//    no per-element branch) and writes them as one contiguous run, one
-//    128-bit store per lane, instead of one scattered store per element.
+//  - pack and write: per chunk, the wave packs its kept elements into its
+//    own LDS row (every element is written somewhere, so no per-element
+//    branch) and writes them as one contiguous run, one 128-bit store per
+//    lane, instead of one scattered store per element.  A place in the row
+//    does not depend on the carry, so the first group of chunks is packed
+//    while wave 0's first look-back poll is in flight; the writes follow the
+//    look-back.
 // The predicate is evaluated once in each pass, one compare per element.
 // Elements past n exist only in the wave that holds n; they are replaced
 // there, once, by a value that is never kept, so no element needs a bound
@@ -133,44 +136,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
     }
     uint32_t wpre, agg, wpref, aggf;
     combine_waves<Op, SH::WAVES>(wave, lane, wsum, 0u, s_wtot, s_wflag, wpre, wpref, agg, aggf);
-    if (multi && wave == 0) {
-      uint64_t *st = ka.status + parity * ka.capacity;
-      publish_first<Op>(st, t, agg, 0u);
-      uint32_t carry = 0u;
-      if (t > 0) {
-        uint64_t w[K];
-        lb_window<Op, K>(st, (int32_t)t - 1, w);
-        carry = look_back<Op, K, K>(st, t, ka.spin_limit, ka.err, w);
-        if (lane == 0) st_agent(st + t, Op::pack(carry + agg, kPrefix));
-      }
-      if (lane == 0) s_carry = carry;
-    }
-    __syncthreads();
-    // carry and base are wave-uniform; saying so keeps the output buffer
-    // resources in scalar registers (a resource the compiler must treat as
-    // per-lane turns every store into a loop over its distinct values)
-    const uint32_t carry = (uint32_t)__builtin_amdgcn_readfirstlane((int)(t > 0 ? s_carry : 0u));
-    if (t == ka.tiles - 1 && tid == 0) *a.count = (int64_t)(carry + agg);
-    // kept elements go to out[carry + wpre + (kept in the wave's earlier
-    // chunks) + (kept in earlier lanes of the chunk) + (kept before k in the group)]
-    const uint32_t base = (uint32_t)__builtin_amdgcn_readfirstlane((int)(carry + wpre));
-    // the kept elements' range out[base, n), clamped to [0, 2^31) bytes: a
-    // start beyond n (only after a look-back that gave up) writes nothing
-    const int64_t kbytes = (ka.n - (int64_t)base) * 4;
-    const bool kok = kbytes > 0;
     uint32_t *stage = s_stage[wave];
-    uint32_t cb = 0u;   // kept in the wave's chunks so far (uniform)
-    // partition: the wave's rejected elements go to out[rlo, rlo + rej) in
-    // reverse order, rlo = n - (rejected before the wave) - (rejected in it);
-    // a range outside [0, n) (only after a look-back that gave up) writes nothing
-    uint32_t rej = 0u, rc = 0u;   // rejected in the wave; in its chunks so far
-    int64_t rlo = 0;
-    bool rok_all = false;
-    if constexpr (PART) {
-      rej = wvalid - wsum;
-      rlo = ka.n - (wb - (int64_t)base) - (int64_t)rej;
-      rok_all = rlo >= 0 && rlo + (int64_t)rej <= ka.n;
-    }
     // The chunks go in groups of FL, each group written as one run.  Row of
     // the wave's LDS staging area for a group: its kept elements in order at
     // [0, kept).  With PART, a rejected element at group index e goes to
@@ -203,6 +169,76 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
         p += kept ? 1u : 0u;
       }
     };
+    // a group's kept elements and its elements that exist (uniform)
+    auto group_kept = [&](const int g0) -> uint32_t {
+      uint32_t kg = 0u;
+#pragma unroll
+      for (int j = 0; j < FL; ++j) kg += field(tot, g0 + j);
+      return kg;
+    };
+    auto group_valid = [&](const int g0) -> uint32_t {
+      const int64_t v64 = (int64_t)wvalid - 256 * g0;
+      return v64 <= 0 ? 0u : (v64 >= KR ? (uint32_t)KR : (uint32_t)v64);
+    };
+    // group g0 .. g0+FL-1 into the wave's row; given the next tile's span
+    // (not nullptr), each chunk's registers take the next tile's chunk
+    // c - KH once it is packed
+    constexpr int KH = SH::CH / 2;
+    using Span = WaveSpan<SH, true, false, VEC>;
+    auto pack_group = [&](const int g0, const auto in) {
+      const uint32_t kg = group_kept(g0), valid = group_valid(g0);
+      uint32_t cg = 0u;
+#pragma unroll
+      for (int j = 0; j < FL; ++j) {
+        pack(g0 + j, cg, (uint32_t)(KR - 1) + (valid - kg) - 256u * (uint32_t)j);
+        cg += field(tot, g0 + j);
+        if constexpr (std::is_pointer_v<decltype(in)>) in->load(g0 + j - KH, R[g0 + j - KH]);
+      }
+    };
+    // publish and issue the first poll; pack the first group (LDS only, its
+    // places do not depend on the carry) while the poll is in flight; then
+    // look back
+    uint64_t w1[1];
+    if (multi && wave == 0) {
+      uint64_t *st = ka.status + parity * ka.capacity;
+      publish_first<Op>(st, t, agg, 0u);
+      if (t > 0) lb_window<Op, 1>(st, (int32_t)t - 1, w1);
+    }
+    pack_group(0, nullptr);
+    if (multi && wave == 0) {
+      uint64_t *st = ka.status + parity * ka.capacity;
+      uint32_t carry = 0u;
+      if (t > 0) {
+        carry = look_back<Op, 1, K>(st, t, ka.spin_limit, ka.err, w1);
+        if (lane == 0) st_agent(st + t, Op::pack(carry + agg, kPrefix));
+      }
+      if (lane == 0) s_carry = carry;
+    }
+    __syncthreads();
+    // carry and base are wave-uniform; saying so keeps the output buffer
+    // resources in scalar registers (a resource the compiler must treat as
+    // per-lane turns every store into a loop over its distinct values)
+    const uint32_t carry = (uint32_t)__builtin_amdgcn_readfirstlane((int)(t > 0 ? s_carry : 0u));
+    if (t == ka.tiles - 1 && tid == 0) *a.count = (int64_t)(carry + agg);
+    // kept elements go to out[carry + wpre + (kept in the wave's earlier
+    // chunks) + (kept in earlier lanes of the chunk) + (kept before k in the group)]
+    const uint32_t base = (uint32_t)__builtin_amdgcn_readfirstlane((int)(carry + wpre));
+    // the kept elements' range out[base, n), clamped to [0, 2^31) bytes: a
+    // start beyond n (only after a look-back that gave up) writes nothing
+    const int64_t kbytes = (ka.n - (int64_t)base) * 4;
+    const bool kok = kbytes > 0;
+    uint32_t cb = 0u;   // kept in the wave's chunks so far (uniform)
+    // partition: the wave's rejected elements go to out[rlo, rlo + rej) in
+    // reverse order, rlo = n - (rejected before the wave) - (rejected in it);
+    // a range outside [0, n) (only after a look-back that gave up) writes nothing
+    uint32_t rej = 0u, rc = 0u;   // rejected in the wave; in its chunks so far
+    int64_t rlo = 0;
+    bool rok_all = false;
+    if constexpr (PART) {
+      rej = wvalid - wsum;
+      rlo = ka.n - (wb - (int64_t)base) - (int64_t)rej;
+      rok_all = rlo >= 0 && rlo + (int64_t)rej <= ka.n;
+    }
     // FL 128-bit stores per lane and run: lane l writes row words 4l .. 4l+3
     // (+256 i) to the run's words 4l .. 4l+3 (+256 i) through a resource that
     // ends at the run's last element (the hardware checks every dword, so a
@@ -234,29 +270,16 @@ __global__ void __launch_bounds__(BLOCK, MINW) compact_tiles(CompactArgs a) {
         rc += nrej;
       }
     };
-    // group g0 .. g0+FL-1; given the next tile's span (not nullptr), each
-    // chunk's registers take the next tile's chunk c - KH once it is packed
-    constexpr int KH = SH::CH / 2;
-    using Span = WaveSpan<SH, true, false, VEC>;
     auto group = [&](const int g0, const auto in) {
-      uint32_t kg = 0u;
-#pragma unroll
-      for (int j = 0; j < FL; ++j) kg += field(tot, g0 + j);
-      const int64_t v64 = (int64_t)wvalid - 256 * g0;
-      const uint32_t valid = v64 <= 0 ? 0u : (v64 >= KR ? (uint32_t)KR : (uint32_t)v64);
-      uint32_t cg = 0u;
-#pragma unroll
-      for (int j = 0; j < FL; ++j) {
-        pack(g0 + j, cg, (uint32_t)(KR - 1) + (valid - kg) - 256u * (uint32_t)j);
-        cg += field(tot, g0 + j);
-        if constexpr (std::is_pointer_v<decltype(in)>) in->load(g0 + j - KH, R[g0 + j - KH]);
-      }
-      flush(kg, valid);
+      pack_group(g0, in);
+      flush(group_kept(g0), group_valid(g0));
     };
-    // the first half goes out while the next tile is taken from the counter,
-    // then the second half's registers take the next tile's chunks
+    // the first group, packed before the carry was known, goes out first;
+    // the rest of the first half while the next tile is taken from the
+    // counter, then the second half's registers take the next tile's chunks
+    flush(group_kept(0), group_valid(0));
 #pragma unroll
-    for (int g0 = 0; g0 < KH; g0 += FL) group(g0, nullptr);
+    for (int g0 = FL; g0 < KH; g0 += FL) group(g0, nullptr);
     int64_t next = ka.tiles;
     if (multi) {
       if (wave == 0) {
