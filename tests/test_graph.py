@@ -23,12 +23,29 @@ def _case(seed, n, S):
 
 @pytest.mark.parametrize("n,S", [(1000, 5), (3_000_001, 700), (40_000_000, 4096)])
 def test_segmented_graph_replays(n, S):
+    _graph_replays(n, S)
+
+
+# the graph captures the configuration chosen at creation: the large-tile
+# segmented kernels, plain (21) and with early publication (35)
+@pytest.mark.parametrize("cfg", [21, 35])
+def test_segmented_graph_replays_config(cfg):
+    _graph_replays(3_000_001, 700, cfg)
+
+
+def _graph_replays(n, S, cfg=None):
     import paper_2312_14874_amd as scan
     a, off = _case(n, n, S)
     x = to_dev(a)
     out = torch.empty_like(x)
     offs = torch.from_numpy(off).cuda()
-    g = scan.SegmentedScanGraph(x, out, offs, exclusive=True)
+    if cfg is not None:
+        scan.force_config(cfg)
+    try:
+        g = scan.SegmentedScanGraph(x, out, offs, exclusive=True)
+    finally:
+        if cfg is not None:
+            scan.force_config(-1)
     want = oracle.segmented_int(a, off, exclusive=True)
     for rep in range(5):
         out.zero_()
