@@ -482,7 +482,8 @@ scan_status_t flat64(const void *in, void *out, int64_t n, scan_dtype_t dt, uint
   if (s != SCAN_SUCCESS) return s;
   s = stream_pending(dev, stream);
   if (s != SCAN_SUCCESS) return s;
-  const int64_t tile = (int64_t)kScan64Block * kScan64Items;
+  const int kind = dt == SCAN_F64 ? 1 : 0;
+  const int64_t tile = (int64_t)kScan64Block[kind] * kScan64Items[kind];
   const int64_t T = tiles_for(n, tile);
   if (2 * T > kMaxTiles) return SCAN_ERROR_NOT_SUPPORTED;
   Workspace *ws = nullptr;
@@ -490,8 +491,8 @@ scan_status_t flat64(const void *in, void *out, int64_t n, scan_dtype_t dt, uint
     s = stream_ws(dev, stream, 2 * T, &ws);
     if (s != SCAN_SUCCESS) return s;
   }
-  const void *fn = kScan64[dt == SCAN_F64 ? 1 : 0][(flags & SCAN_REVERSE) ? 1 : 0];
-  const int64_t grid = std::min<int64_t>(T, resident_grid(fn, kScan64Block, di.cus, 0, 100));
+  const void *fn = kScan64[kind][(flags & SCAN_REVERSE) ? 1 : 0];
+  const int64_t grid = std::min<int64_t>(T, resident_grid(fn, kScan64Block[kind], di.cus, 0, 100));
   KernelArgs a;
   std::memset(&a, 0, sizeof(a));
   a.in = in;
@@ -509,7 +510,7 @@ scan_status_t flat64(const void *in, void *out, int64_t n, scan_dtype_t dt, uint
   a.err = ws ? ws->err : nullptr;
   a.exclusive = (flags & SCAN_EXCLUSIVE) ? 1u : 0u;
   void *args[] = {&a};
-  hipError_t e = hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kScan64Block), args, 0, stream);
+  hipError_t e = hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kScan64Block[kind]), args, 0, stream);
   return e == hipSuccess ? SCAN_SUCCESS : hip_fail(e);
 }
 

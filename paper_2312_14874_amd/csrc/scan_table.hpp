@@ -62,6 +62,6 @@ extern const CompactKernels kPartition;   // two-way partition (set_count unused
 // 64-bit scans (flat, 16-byte aligned buffers): [0 = integer sum, 1 = float64
 // sum][reverse].
 extern const void *kScan64[2][2];
-extern const int kScan64Block, kScan64Items;
+extern const int kScan64Block[2], kScan64Items[2];   // [0 = integer, 1 = float64]
 
 }  // namespace mi355scan
